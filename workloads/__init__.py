@@ -1,0 +1,92 @@
+"""Seeded synthetic inputs shaped like the paper's timing workloads.
+
+This module only draws random numbers and arranges them into matrices; it
+holds none of the pivoting arithmetic.  Both the oracle-based checks and the
+HIP path take their inputs from here, so that they see identical bits.
+
+The paper times random dense supernodes (Section 7.1: p = 512 with n up to
+100000, and n = 100000 with p up to 1024) without giving their
+construction.  The recipes here are:
+
+* supernode(n, p): A11 = tril(G) + tril(G,-1)^T with G ~ N(0,1)^(p x p),
+  then a chosen number of diagonal entries (distinct, uniformly drawn)
+  multiplied by a small factor so that some 1x1 candidates fail and 2x2
+  pivots and delays occur; A21 ~ N(0,1)^((n-p) x p).  Draw order: G, the
+  diagonal indices, A21.
+* dense_indefinite(N): Q diag(lam) Q^T with Q the orthogonal factor of a
+  Gaussian matrix (Householder QR, signs fixed by diag(R)) and lam half
+  negative, half positive, |lam| ~ U[lo, 1], shuffled.
+* batch of supernodes: n log-uniform, p uniform with p <= n/4.
+
+Every array is float64, row index first (n x p); the binding stores panels
+column-major on the device.
+"""
+
+import numpy as np
+
+
+def supernode(n, p, seed=0, n_small=0, small_scale=1e-8):
+    """n x p supernode [A11; A21] (A11 stored as a full symmetric block)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((p, p))
+    A11 = np.tril(G) + np.tril(G, -1).T
+    if n_small:
+        idx = rng.choice(p, n_small, replace=False)
+        A11[idx, idx] *= small_scale
+    A21 = rng.standard_normal((n - p, p))
+    return np.vstack([A11, A21])
+
+
+def small_supernode(seed=0):
+    """n = 256, p = 32: four diagonal entries scaled by 1e-8."""
+    return supernode(256, 32, seed, n_small=4, small_scale=1e-8)
+
+
+def large_supernode(seed=0):
+    """n = 100000, p = 512: 2% of the diagonal (10 entries) scaled by 1e-6."""
+    return supernode(100000, 512, seed, n_small=int(0.02 * 512), small_scale=1e-6)
+
+
+def dense_indefinite(N, seed=0, lam_lo=1e-3, nrhs=0):
+    """Symmetric indefinite Q diag(lam) Q^T, half the eigenvalues negative.
+
+    Returns (A, lam) or (A, lam, B) when nrhs > 0 with B ~ N(0,1)^(N x nrhs).
+    """
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((N, N))
+    Q, R = np.linalg.qr(Z)
+    Q = Q * np.sign(np.diag(R))
+    half = N // 2
+    lam = np.concatenate([-rng.uniform(lam_lo, 1.0, half),
+                          rng.uniform(lam_lo, 1.0, N - half)])
+    rng.shuffle(lam)
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    if nrhs:
+        B = rng.standard_normal((N, nrhs))
+        return A, lam, B
+    return A, lam
+
+
+def batch_shapes(count, seed=0, n_lo=64, n_hi=8192, p_lo=8, p_hi=256):
+    """Shapes of a batch of independent supernodes: n log-uniform in
+    [n_lo, n_hi], p uniform in [p_lo, min(p_hi, n // 4)]."""
+    rng = np.random.default_rng(seed)
+    ns, ps = [], []
+    for _ in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        p = int(rng.integers(p_lo, min(p_hi, n // 4) + 1))
+        ns.append(n)
+        ps.append(p)
+    return np.array(ns), np.array(ps)
+
+
+def batch_panel(n, p, rng, small_prob=0.01, small_scale=1e-8):
+    """One supernode of a batch, drawn from a shared generator: tril-reflected
+    A11, each diagonal entry scaled with probability small_prob."""
+    G = rng.standard_normal((p, p))
+    A11 = np.tril(G) + np.tril(G, -1).T
+    mask = rng.random(p) < small_prob
+    A11[mask, mask] *= small_scale
+    A21 = rng.standard_normal((n - p, p))
+    return np.vstack([A11, A21])
