@@ -1,0 +1,373 @@
+// Compression of A21 into the p x p matrix C (Section 4, Fig. 4.1 (a)-(b)).
+//
+// Both constructions use comparisons only, so C is exact.
+//
+// Strict (Section 4.1, eq. (4.2)): two streaming passes over A21.
+//   pass 1: one thread per row finds the column of its largest |a(i,k)|
+//           (first maximum) -> set index J[i];
+//   pass 2: workgroups own (row chunk, 8 columns); each folds |a(i,k)| into
+//           an LDS table indexed by (J[i], k) with 64-bit atomic max on the
+//           IEEE bit patterns (monotone for values >= 0), then merges the
+//           table into C in global memory with atomic max.
+//   The paper reduces partial C matrices on a tree across processors; on
+//   one GPU the reduction tree is lanes -> LDS -> L2 atomics.
+//
+// Relaxed (Section 4.2): row j of C is the largest unflagged entry's row
+//   of column j, taken in column order with flagging.  The row chosen for
+//   column j is the best of column j once at most j rows are excluded, so
+//   it is among column j's top j+1 rows.  Pass 1 keeps, per (column, row
+//   chunk), the top RELAXED_TOPK (|a|, row) pairs in the total order
+//   "larger value first, lower row first"; pass 2 (one workgroup) merges
+//   them per column, walks the columns in order taking the first unflagged
+//   candidate, rescans a column in full in the rare case that all its
+//   candidates are taken, and gathers the chosen signed rows into C.
+
+#include "common.h"
+
+namespace ctp {
+
+constexpr int STRICT_CG = 8;          // columns per workgroup in pass 2
+constexpr int STRICT_ROWS = 4096;     // rows per workgroup in pass 2
+constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block
+
+int relaxed_chunk_count(int rows) { return rows <= 0 ? 1 : (rows + RELAXED_CHUNK - 1) / RELAXED_CHUNK; }
+
+__global__ void fill_u64_kernel(unsigned long long* x, size_t count, unsigned long long v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) x[i] = v;
+}
+
+__global__ void fill_i32_kernel(int* x, int count, int v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) x[i] = v;
+}
+
+__global__ __launch_bounds__(256) void strict_rowset_kernel(int r, int p, const double* __restrict__ a21,
+                                                          int lda, int* __restrict__ J,
+                                                          int* __restrict__ status) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= r) return;
+  const double* row = a21 + i;
+  double best = -1.0;
+  int bj = 0;
+  bool finite = true;
+  int k = 0;
+  for (; k + 4 <= p; k += 4) {
+    double v0 = fabs(row[(size_t)(k + 0) * lda]);
+    double v1 = fabs(row[(size_t)(k + 1) * lda]);
+    double v2 = fabs(row[(size_t)(k + 2) * lda]);
+    double v3 = fabs(row[(size_t)(k + 3) * lda]);
+    finite = finite && isfinite(v0) && isfinite(v1) && isfinite(v2) && isfinite(v3);
+    if (v0 > best) { best = v0; bj = k; }
+    if (v1 > best) { best = v1; bj = k + 1; }
+    if (v2 > best) { best = v2; bj = k + 2; }
+    if (v3 > best) { best = v3; bj = k + 3; }
+  }
+  for (; k < p; ++k) {
+    double v = fabs(row[(size_t)k * lda]);
+    finite = finite && isfinite(v);
+    if (v > best) { best = v; bj = k; }
+  }
+  J[i] = bj;
+  if (!finite) atomicOr(status, ST_NONFINITE);
+}
+
+// Dynamic LDS: p * STRICT_CG u64 bins.
+__global__ __launch_bounds__(256) void strict_colmax_kernel(int r, int p, const double* __restrict__ a21,
+                                                          int lda, const int* __restrict__ J,
+                                                          unsigned long long* __restrict__ cbits, int ldc) {
+  extern __shared__ unsigned long long bins[];
+  const int k0 = blockIdx.y * STRICT_CG;
+  const int ncol = min(STRICT_CG, p - k0);
+  const int i0 = blockIdx.x * STRICT_ROWS;
+  const int i1 = min(r, i0 + STRICT_ROWS);
+  for (int q = threadIdx.x; q < p * STRICT_CG; q += blockDim.x) bins[q] = 0ull;
+  __syncthreads();
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int j = J[i];
+    unsigned long long* b = bins + (size_t)j * STRICT_CG;
+#pragma unroll
+    for (int c = 0; c < STRICT_CG; ++c) {
+      if (c < ncol) {
+        unsigned long long v = abs_bits(a21[(size_t)(k0 + c) * lda + i]);
+        if (v) atomicMax(b + c, v);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < p * STRICT_CG; q += blockDim.x) {
+    unsigned long long v = bins[q];
+    int j = q / STRICT_CG, c = q % STRICT_CG;
+    if (v && c < ncol) atomicMax(cbits + (size_t)(k0 + c) * ldc + j, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Relaxed compression
+// ---------------------------------------------------------------------------
+
+struct Cand {
+  double v;   // |a(i, j)|, or -1 for "none"
+  int i;      // row of A21
+};
+
+CTP_DEV bool better(double v1, int i1, double v2, int i2) {
+  return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+
+// Grid (column, chunk).  Writes RELAXED_TOPK candidates per (column, chunk)
+// to cand[(col * nchunks + chunk) * K + q], best first; missing -> v = -1.
+__global__ __launch_bounds__(256) void relaxed_topk_kernel(int r, int p, const double* __restrict__ a21,
+                                                         int lda, int nchunks, Cand* __restrict__ cand,
+                                                         int* __restrict__ status) {
+  constexpr int K = RELAXED_TOPK;
+  const int col = blockIdx.x;
+  const int chunk = blockIdx.y;
+  const int i0 = chunk * RELAXED_CHUNK;
+  const int i1 = min(r, i0 + RELAXED_CHUNK);
+  const double* colp = a21 + (size_t)col * lda;
+
+  double tv[K];
+  int ti[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) { tv[q] = -1.0; ti[q] = 0x7fffffff; }
+  bool finite = true;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    double v = fabs(colp[i]);
+    finite = finite && isfinite(v);
+    if (better(v, i, tv[K - 1], ti[K - 1])) {
+      // insertion into the sorted list (static indices only)
+      double cv = v;
+      int ci = i;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        if (better(cv, ci, tv[q], ti[q])) {
+          double sv = tv[q];
+          int si = ti[q];
+          tv[q] = cv; ti[q] = ci;
+          cv = sv; ci = si;
+        }
+      }
+    }
+  }
+  if (!finite) atomicOr(status, ST_NONFINITE);
+
+  // Workgroup merge: K rounds of "best head among all threads".
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  __shared__ double wv;
+  __shared__ int wi;
+  int head = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int q = 0; q < K; ++q) {
+    double hv = -1.0;
+    int hi = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < K; ++s)
+      if (s == head) { hv = tv[s]; hi = ti[s]; }
+    double bv = hv;
+    int bi = hi;
+    for (int off = 32; off > 0; off >>= 1) {
+      double ov = __shfl_xor(bv, off, 64);
+      int oi = __shfl_xor(bi, off, 64);
+      if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { sv[wave] = bv; si[wave] = bi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double xv = sv[0];
+      int xi = si[0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (better(sv[w], si[w], xv, xi)) { xv = sv[w]; xi = si[w]; }
+      wv = xv; wi = xi;
+      Cand* out = cand + ((size_t)col * nchunks + chunk) * K + q;
+      out->v = xv;
+      out->i = (xv < 0.0) ? -1 : xi;
+    }
+    __syncthreads();
+    if (wv >= 0.0 && hi == wi && hv == wv) ++head;   // the winner pops its head
+    __syncthreads();
+  }
+}
+
+// One workgroup of 1024 threads.  Dynamic LDS: final candidate lists
+// (p * K Cand) + chosen rows (p ints).
+__global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, const double* __restrict__ a21,
+                                                            int lda, int nchunks,
+                                                            const Cand* __restrict__ cand,
+                                                            double* __restrict__ c, int ldc,
+                                                            int* __restrict__ crow_out,
+                                                            int* __restrict__ status) {
+  constexpr int K = RELAXED_TOPK;
+  extern __shared__ unsigned char smem[];
+  Cand* lists = reinterpret_cast<Cand*>(smem);
+  int* chosen = reinterpret_cast<int*>(lists + (size_t)p * K);
+  __shared__ int s_pick;
+  __shared__ int s_need_scan;
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+
+  // 1. Merge the chunk lists of each column into its global top K.
+  for (int col = threadIdx.x; col < p; col += blockDim.x) {
+    double tv[K];
+    int ti[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) { tv[q] = -1.0; ti[q] = 0x7fffffff; }
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const Cand* src = cand + ((size_t)col * nchunks + ch) * K;
+      for (int q = 0; q < K; ++q) {
+        Cand e = src[q];
+        if (e.v < 0.0) break;
+        if (!better(e.v, e.i, tv[K - 1], ti[K - 1])) break;   // lists are sorted
+        double cv = e.v;
+        int ci = e.i;
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+          if (better(cv, ci, tv[s], ti[s])) {
+            double sv = tv[s];
+            int si = ti[s];
+            tv[s] = cv; ti[s] = ci;
+            cv = sv; ci = si;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      lists[(size_t)col * K + q].v = tv[q];
+      lists[(size_t)col * K + q].i = tv[q] < 0.0 ? -1 : ti[q];
+    }
+  }
+  __syncthreads();
+
+  // 2. Column order with flagging.  Wave 0 tests candidates against the
+  //    rows already chosen; a column whose K candidates are all taken is
+  //    rescanned by the whole workgroup.
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = blockDim.x >> 6;
+  int taken = 0;                       // rows chosen so far (== j unless rows ran out)
+  for (int j = 0; j < p; ++j) {
+    if (threadIdx.x == 0) { s_pick = -1; s_need_scan = 0; }
+    __syncthreads();
+    if (taken >= r) {
+      if (threadIdx.x == 0) chosen[j] = -1;
+      __syncthreads();
+      continue;
+    }
+    if (wave == 0) {
+      int pick = -1;
+      for (int q = 0; q < K && pick < 0; ++q) {
+        int cand_row = lists[(size_t)j * K + q].i;
+        if (cand_row < 0) break;
+        bool hit = false;
+        for (int s = lane; s < j; s += 64) hit = hit || (chosen[s] == cand_row);
+        unsigned long long any = __ballot(hit);
+        if (!any) pick = cand_row;
+      }
+      if (lane == 0) {
+        if (pick >= 0) s_pick = pick;
+        else s_need_scan = 1;
+      }
+    }
+    __syncthreads();
+    if (s_need_scan) {
+      // Full rescan of column j over rows not yet chosen.
+      const double* colp = a21 + (size_t)j * lda;
+      double bv = -1.0;
+      int bi = 0x7fffffff;
+      for (int i = threadIdx.x; i < r; i += blockDim.x) {
+        double v = fabs(colp[i]);
+        if (!better(v, i, bv, bi)) continue;
+        bool hit = false;
+        for (int s = 0; s < j; ++s) hit = hit || (chosen[s] == i);
+        if (!hit) { bv = v; bi = i; }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        double ov = __shfl_xor(bv, off, 64);
+        int oi = __shfl_xor(bi, off, 64);
+        if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double xv = red_v[0];
+        int xi = red_i[0];
+        for (int w = 1; w < nwaves; ++w)
+          if (better(red_v[w], red_i[w], xv, xi)) { xv = red_v[w]; xi = red_i[w]; }
+        s_pick = (xv >= 0.0) ? xi : -1;
+        atomicOr(status, ST_RELAXED_RESCAN);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) chosen[j] = s_pick;
+    __syncthreads();
+    if (s_pick >= 0) ++taken;
+  }
+
+  // 3. Gather the chosen signed rows into C (zero rows when none).
+  for (int q = threadIdx.x; q < p * p; q += blockDim.x) {
+    int j = q % p, k = q / p;    // consecutive threads walk down a column of C
+    int row = chosen[j];
+    c[(size_t)k * ldc + j] = row >= 0 ? a21[(size_t)k * lda + row] : 0.0;
+  }
+  if (crow_out)
+    for (int j = threadIdx.x; j < p; j += blockDim.x) crow_out[j] = chosen[j];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+int launch_compress(int n, int p, const double* a, int lda, int method, double* c, int ldc,
+                    int* crow, int* status, void* work, hipStream_t stream) {
+  const int r = n - p;
+  const double* a21 = a + p;
+  Workspace ws = workspace_layout(n, p, method);
+  unsigned char* base = static_cast<unsigned char*>(work);
+  if (method == CTP_STRICT) {
+    int* J = reinterpret_cast<int*>(base + ws.j_off);
+    size_t cnt = (size_t)ldc * p;
+    fill_u64_kernel<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, stream>>>(
+        reinterpret_cast<unsigned long long*>(c), cnt, 0ull);
+    if (r > 0) {
+      strict_rowset_kernel<<<(r + 255) / 256, 256, 0, stream>>>(r, p, a21, lda, J, status);
+      dim3 grid((r + STRICT_ROWS - 1) / STRICT_ROWS, (p + STRICT_CG - 1) / STRICT_CG);
+      size_t lds = (size_t)p * STRICT_CG * sizeof(unsigned long long);
+      if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)strict_colmax_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+      }
+      strict_colmax_kernel<<<grid, 256, lds, stream>>>(r, p, a21, lda, J,
+                                                       reinterpret_cast<unsigned long long*>(c), ldc);
+    }
+  } else if (method == CTP_RELAXED) {
+    Cand* cand = reinterpret_cast<Cand*>(base + ws.cand_off);
+    int nch = ws.relaxed_chunks;
+    if (r > 0) {
+      dim3 grid(p, nch);
+      relaxed_topk_kernel<<<grid, 256, 0, stream>>>(r, p, a21, lda, nch, cand, status);
+    }
+    size_t lds = (size_t)p * RELAXED_TOPK * sizeof(Cand) + (size_t)p * sizeof(int);
+    if (r > 0 && lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)relaxed_select_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+    }
+    if (r > 0) {
+      relaxed_select_kernel<<<1, 1024, lds, stream>>>(r, p, a21, lda, nch, cand, c, ldc, crow, status);
+    } else {
+      size_t cnt = (size_t)ldc * p;
+      fill_u64_kernel<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, stream>>>(
+          reinterpret_cast<unsigned long long*>(c), cnt, 0ull);
+      if (crow) fill_i32_kernel<<<(p + 255) / 256, 256, 0, stream>>>(crow, p, -1);
+    }
+  } else {
+    return -5;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+}  // namespace ctp

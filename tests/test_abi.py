@@ -1,0 +1,71 @@
+"""The C interface on the CPU: the library loads, exports every symbol that
+include/ctp.h declares, and its host-side argument checks behave as the
+header documents.  No call here reaches the GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ctp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctp_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1305_2353_amd import ctp
+    if not os.path.exists(ctp.LIB_PATH):
+        pytest.skip("libctp.so not built")
+    return ctp.load()
+
+
+def test_header_declares_the_binding_names():
+    from paper_1305_2353_amd import ctp
+    assert _declared() == sorted(ctp.EXPORTED)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_default_opts(lib):
+    from paper_1305_2353_amd import ctp
+    o = ctp.CtpOpts()
+    lib.ctp_default_opts(ctypes.byref(o))
+    assert (o.method, o.u, o.small, o.prec, o.tile) == (ctp.CTP_RELAXED, 0.01, 1e-20, 0, -1)
+    assert "gfx950" in ctp.ctp_version()
+
+
+def test_workspace_size_and_argument_checks(lib):
+    from paper_1305_2353_amd import ctp
+    o = ctp.ctp_default_opts("strict")
+    sz = ctypes.c_size_t()
+    assert lib.ctp_workspace_size(100, 10, ctypes.byref(o), ctypes.byref(sz)) == 0
+    assert sz.value >= 10 * 10 * 8 + 90 * 4
+    assert lib.ctp_workspace_size(5, 10, ctypes.byref(o), ctypes.byref(sz)) == -1
+    assert lib.ctp_workspace_size(10, -1, ctypes.byref(o), ctypes.byref(sz)) == -2
+    bad = ctp.ctp_default_opts("relaxed", u=0.7)
+    assert lib.ctp_workspace_size(10, 5, ctypes.byref(bad), ctypes.byref(sz)) == -3
+    bad = ctp.ctp_default_opts("relaxed", u=0.0)
+    assert lib.ctp_workspace_size(10, 5, ctypes.byref(bad), ctypes.byref(sz)) == -3
+    # factor: invalid arguments are rejected on the host before any launch
+    nul = ctypes.c_void_p(0)
+    assert lib.ctp_factor_supernode(5, 10, nul, 5, ctypes.byref(o), nul, nul, nul, nul, nul, nul, 0, nul) == -1
+    assert lib.ctp_factor_supernode(20, 10, nul, 20, ctypes.byref(o), nul, nul, nul, nul, nul, nul, 0, nul) == -3
+    fake = ctypes.c_void_p(4096)
+    assert lib.ctp_factor_supernode(20, 10, fake, 19, ctypes.byref(o), fake, fake, fake, fake, fake, fake,
+                                    1 << 20, nul) == -4
+    assert lib.ctp_factor_supernode(20, 10, fake, 20, ctypes.byref(o), fake, fake, fake, fake, fake, fake,
+                                    0, nul) == -12
+    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 5, 6, fake, 6, ctypes.byref(o), nul) == -9
+    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 0, 6, fake, 5, ctypes.byref(o), nul) == -11
+    assert lib.ctp_solve_supernode(600, 513, fake, 600, fake, fake, fake, fake, ctypes.byref(o), nul) == -2
+    assert lib.ctp_compress(20, 10, fake, 20, 0, fake, 10, fake, fake, fake, 1 << 20, nul) == -5
