@@ -156,14 +156,15 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_f64_kernel(SchurArgs g) {
     __syncthreads();
   }
 
-  // ---- epilogue: lane holds rows 4*(lane/16)+q, column lane%16 of each block
+  // ---- epilogue: for v_mfma_f64_16x16x4, accumulator element q of lane l
+  //      is row l/16 + 4q, column l%16 of the 16 x 16 block
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = i0 + wm * 64 + x * 16 + 4 * lk + q;
+        const int i = i0 + wm * 64 + x * 16 + lk + 4 * q;
         const int j = j0 + wn * 64 + y * 16 + lrow;
         if (i < iend && j <= i) g.s[(size_t)j * g.lds + (i - g.row0)] = acc[x][y][q];
       }
