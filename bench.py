@@ -1,0 +1,224 @@
+"""Benchmark: one supernode n = 100000, p = 512 through the whole hot path.
+
+One step (all on the GPU, inputs resident in HBM):
+    stage    copy the pristine panel into the working panel (in-place method)
+    factor   compression of A21 + pivot search on [A11; C]   (ctp_factor_supernode)
+    solve    L21 and the delayed columns                      (ctp_solve_supernode)
+    form     S = L21 D L21^T, lower triangle, in 4096-row blocks written to
+             one reused block buffer                          (ctp_schur x 25)
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--method relaxed]
+
+Prints one JSON line.  `value` is algorithmic GFLOP/s of the step:
+    p^3/3 (A11 factor) + (n-p) nelim^2 (triangular solve)
+    + 2 (n-p) nelim (p-nelim) (delayed columns) + (n-p)(n-p+1) nelim (Form),
+with no credit for compression or pivot tests.  `roofline` is measured on
+the Form kernel (the dominant one) with HIP events around every launch.
+Also reported: the TPP baseline on the same panel, phase times, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Supernode LDLT GF/s,%roofline: compressed vs TPP; mixed vs FP64 @bwd err 1e-14"
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix
+PEAK_HBM_GBS = 8000.0
+BLOCK_ROWS = 4096
+
+
+def algorithmic_flops(n, p, nelim):
+    r = n - p
+    return (p ** 3) / 3.0 + r * nelim ** 2 + 2.0 * r * nelim * (p - nelim) + r * (r + 1.0) * nelim
+
+
+def schur_block_flops(row0, nrows, nelim):
+    entries = nrows * row0 + nrows * (nrows + 1) / 2.0
+    return 2.0 * nelim * entries
+
+
+def cpu_baseline(A, p, method, blocks):
+    """The oracle as it stands, on the host: Factor + Solve of the full
+    panel plus the Form rows of the given 4096-row blocks."""
+    from oracle.supernode import factor_supernode, schur_block
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([d.get("num_threads", 0) for d in info] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    n = A.shape[0]
+    r = n - p
+    t0 = time.perf_counter()
+    F = factor_supernode(A, p, method)
+    flops = (p ** 3) / 3.0 + r * F.nelim ** 2 + 2.0 * r * F.nelim * (p - F.nelim)
+    for b in blocks:
+        row0 = b * BLOCK_ROWS
+        nr = min(BLOCK_ROWS, r - row0)
+        schur_block(F, row0, nr)
+        flops += schur_block_flops(row0, nr, F.nelim)
+    dt = time.perf_counter() - t0
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": f"full Factor+Solve ({method}) of the n={n}, p={p} panel plus Form rows of "
+                      f"4096-row blocks {list(blocks)} of {-(-r // BLOCK_ROWS)}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--method", default="relaxed", choices=["relaxed", "strict", "restricted"])
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--p", type=int, default=512)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tpp", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the supernode path runs on a single MI355X "
+              "(see the design notes for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1305_2353_amd import ctp
+    from workloads import large_supernode, supernode
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, p = args.n, args.p
+    if (n, p) == (100000, 512):
+        A = large_supernode(args.seed)
+    else:
+        A = supernode(n, p, args.seed, n_small=int(0.02 * p), small_scale=1e-6)
+    r = n - p
+    pristine = ctp.device_panel(A)
+    a = ctp.device_panel(A)
+    opts = ctp.ctp_default_opts(args.method)
+    work = ctp.workspace(n, p, opts)
+    outs = ctp._outputs(p, dev)
+    S = torch.empty((r, BLOCK_ROWS), dtype=torch.float64, device=dev).t()   # lds = 4096
+    blocks = [(b * BLOCK_ROWS, min(BLOCK_ROWS, r - b * BLOCK_ROWS)) for b in range(-(-r // BLOCK_ROWS))]
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        ev = events
+        if ev is not None:
+            ev["t0"].record(stream)
+        a.copy_(pristine)
+        if ev is not None:
+            ev["t1"].record(stream)
+        f = ctp.ctp_factor_supernode(a, opts, work=work, outs=outs)
+        if ev is not None:
+            ev["t2"].record(stream)
+        ctp.ctp_solve_supernode(a, f, opts)
+        if ev is not None:
+            ev["t3"].record(stream)
+        for bi, (row0, nr) in enumerate(blocks):
+            if ev is not None:
+                ev["s"][bi][0].record(stream)
+            ctp.ctp_schur(a, f, row0, nr, opts, s=S[:nr, :row0 + nr])
+            if ev is not None:
+                ev["s"][bi][1].record(stream)
+        if ev is not None:
+            ev["t4"].record(stream)
+        return f
+
+    def new_events():
+        E = lambda: torch.cuda.Event(enable_timing=True)
+        return {"t0": E(), "t1": E(), "t2": E(), "t3": E(), "t4": E(), "s": [(E(), E()) for _ in blocks]}
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # Timed region: exactly `steps` steps.
+    evs = [new_events() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        f = step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    nelim = int(f["nelim"].item())
+    status = int(f["status"].item())
+
+    flops = algorithmic_flops(n, p, nelim)
+    phase = {"stage": 0.0, "factor": 0.0, "solve": 0.0, "form": 0.0}
+    sch_ms = 0.0
+    for e in evs:
+        phase["stage"] += e["t0"].elapsed_time(e["t1"])
+        phase["factor"] += e["t1"].elapsed_time(e["t2"])
+        phase["solve"] += e["t2"].elapsed_time(e["t3"])
+        phase["form"] += e["t3"].elapsed_time(e["t4"])
+        sch_ms += sum(s0.elapsed_time(s1) for s0, s1 in e["s"])
+    phase = {k: round(v / args.steps, 4) for k, v in phase.items()}
+    sch_flops = sum(schur_block_flops(row0, nr, nelim) for row0, nr in blocks)
+    launches = len(blocks)
+    avg_launch_ms = sch_ms / args.steps / launches
+    achieved = (sch_flops / launches) / (avg_launch_ms * 1e-3) / 1e12
+    value = flops / (ms_per_step * 1e-3) / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"supernode n={n} p={p} ({args.method} compressed pivoting, u=0.01): "
+                               f"Factor+Solve+Form, S in {BLOCK_ROWS}-row blocks",
+                   "n": n, "p": p, "method": args.method, "seed": args.seed, "nelim": nelim,
+                   "delayed": p - nelim, "status": status},
+        "roofline": {"bound": "mfma", "kernel": "schur_f64_kernel", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                     "traffic": None, "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": launches},
+        "phases_ms": phase,
+        "algorithmic_gflop_per_step": round(flops / 1e9, 2),
+    }
+
+    if not args.no_tpp:
+        # TPP baseline (Section 2) on the same panel: Factor+Solve in one pass.
+        topts = ctp.ctp_default_opts("tpp")
+        tw = ctp.workspace(n, p, topts)
+        tout = ctp._outputs(p, dev)
+        a.copy_(pristine)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        tf = ctp.ctp_factor_supernode(a, topts, work=tw, outs=tout)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tpp_ms = e0.elapsed_time(e1)
+        cmp_ms = phase["factor"] + phase["solve"]
+        result["tpp"] = {"factor_solve_ms": round(tpp_ms, 3), "nelim": int(tf["nelim"].item()),
+                         "compressed_factor_solve_ms": round(cmp_ms, 3),
+                         "speedup_compressed_vs_tpp": round(tpp_ms / cmp_ms, 2) if cmp_ms > 0 else None}
+
+    if not args.no_cpu_baseline:
+        nb = len(blocks)
+        sample = list(range(0, nb, 2))      # every other 4096-row block of S
+        result["cpu_baseline"] = cpu_baseline(A, p, args.method, sample)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
