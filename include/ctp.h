@@ -88,7 +88,7 @@ typedef struct ctp_opts {
   double u;        /* threshold, 0 < u <= 0.5 (Section 2; default 0.01) */
   double small;    /* entries below small count as zero (default 1e-20) */
   int prec;        /* reserved: 0 = FP64 arithmetic everywhere */
-  int tile;        /* reserved: Form tile configuration, -1 = default */
+  int tile;        /* Form kernel staging variant: -1 or 0 = default, 1 = alternate */
   unsigned flags;  /* reserved, 0 */
 } ctp_opts;
 

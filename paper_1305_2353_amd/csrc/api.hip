@@ -15,7 +15,8 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
                  const double* d, const int* nelim, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
-                 const int* nelim, int row0, int nrows, double* s, int lds, hipStream_t stream);
+                 const int* nelim, int row0, int nrows, double* s, int lds, int tile,
+                 hipStream_t stream);
 
 __global__ void clear_status_kernel(int* status) { *status = 0; }
 
@@ -182,7 +183,7 @@ int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const doub
   if (lds < (nrows > 1 ? nrows : 1)) return -11;
   if (check_opts(opts)) return -12;
   if (nrows == 0) return 0;
-  return launch_schur(n, p, a, lda, piv, d, nelim, row0, nrows, s, lds, stream);
+  return launch_schur(n, p, a, lda, piv, d, nelim, row0, nrows, s, lds, opts->tile, stream);
 }
 
 }  // extern "C"

@@ -7,7 +7,10 @@
 //
 // Tiling: 128 x 128 output tile per workgroup of 4 waves (2 x 2), each wave
 // a 64 x 64 block of 4 x 4 v_mfma_f64_16x16x4 accumulators; K streamed in
-// chunks of 16 through double-buffered LDS with register prefetch.  Tiles
+// chunks of 16 through double-buffered LDS with register prefetch.  The
+// prefetch loads are issued unconditionally from clamped addresses and only
+// consumed after the chunk's MFMAs, so their latency overlaps the matrix
+// work (masking and the D scaling happen on the way into LDS).  Tiles
 // are walked in groups of 8 row tiles (all column tiles of a group before
 // the next group) and each XCD gets a contiguous range of that order, so
 // the 64 tiles resident on one XCD share 8 row panels and 8 column panels
@@ -21,7 +24,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int SC_BM = 128;
 constexpr int SC_BN = 128;
-constexpr int SC_BK = 16;
 constexpr int SC_THREADS = 256;
 constexpr int SC_GROUP = 8;
 constexpr int SC_NXCD = 8;
@@ -41,9 +43,14 @@ struct SchurArgs {
   int per_xcd;      // tiles per XCD range
 };
 
+template <int BK, int RPT>
 __global__ __launch_bounds__(SC_THREADS, 2) void schur_f64_kernel(SchurArgs g) {
-  __shared__ double As[2][SC_BK][SC_BM];
-  __shared__ double Bs[2][SC_BK][SC_BN];
+  // RPT consecutive rows per thread; KPT k rows per thread and operand
+  constexpr int TPK = SC_BM / RPT;        // threads per k row
+  constexpr int KSTEP = SC_THREADS / TPK; // k rows covered by all threads at once
+  constexpr int KPT = BK / KSTEP;
+  __shared__ double As[2][BK][SC_BM];
+  __shared__ double Bs[2][BK][SC_BN];
   __shared__ int piv_s[CTP_MAX_P + 1];
   __shared__ double d_s[2 * CTP_MAX_P + 2];
 
@@ -78,48 +85,54 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_f64_kernel(SchurArgs g) {
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // staging: thread covers k rows {kq, kq+8} and 4 consecutive i/j
-  const int kq = tid / 32;            // 0..7
-  const int ii = (tid % 32) * 4;      // 0..124
+  // staging: consecutive threads take consecutive rows (one 1 KB column
+  // segment per 128 threads); thread covers k rows kq, kq+2, ..., kq+BK-2
+  const int ii = (tid % TPK) * RPT;
+  const int kq = tid / TPK;
 
-  double ra[2][4], rb[2][4];
-  const int nk = (nelim + SC_BK - 1) / SC_BK;
+  // Prefetch registers: raw L21 values only.  Every load is issued
+  // unconditionally from a clamped, in-bounds address so that none waits on
+  // another; masks and the D scaling (W = L21 D) are applied when the
+  // values are written to LDS, after the MFMAs of the current chunk.
+  double ra[KPT][RPT], rb[KPT][RPT], rp[KPT][RPT];
+  double c0[KPT], c1[KPT];
+  bool kv[KPT];
+  const int nk = (nelim + BK - 1) / BK;
+  const int rmax = g.r - 1;
 
   auto load = [&](int kc) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = kc * SC_BK + kq + 8 * h;
+    for (int h = 0; h < KPT; ++h) {
+      const int k = kc * BK + kq + KSTEP * h;
       const bool kval = k < nelim;
-      const int pt = kval ? piv_s[k] : PIV_DELAYED;
-      // W column k from one or two L21 columns
-      double c0 = 0.0, c1 = 0.0;
-      int kp = k;
-      if (pt == PIV_1X1) { c0 = d_s[2 * k]; }
-      else if (pt == PIV_2X2_FIRST) { c0 = d_s[2 * k]; c1 = d_s[2 * k + 1]; kp = k + 1; }
-      else if (pt == PIV_2X2_SECOND) { c0 = d_s[2 * (k - 1) + 2]; c1 = d_s[2 * (k - 1) + 1]; kp = k - 1; }
+      const int pt = kval ? piv_s[k] : PIV_ZERO;
+      const int kp = pt == PIV_2X2_FIRST ? k + 1 : (pt == PIV_2X2_SECOND ? k - 1 : k);
+      const double dk = d_s[2 * (kval ? k : 0)];
+      const double dk1 = d_s[2 * (kval ? k : 0) + 1];
+      const double dm1 = d_s[2 * (kval ? kp : 0) + 1];
+      c0[h] = (pt == PIV_ZERO) ? 0.0 : dk;
+      c1[h] = pt == PIV_2X2_FIRST ? dk1 : (pt == PIV_2X2_SECOND ? dm1 : 0.0);
+      kv[h] = kval;
       const double* colA = g.l21 + (size_t)(kval ? k : 0) * g.lda;
       const double* colP = g.l21 + (size_t)(kval ? kp : 0) * g.lda;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = i0 + ii + e;
-        ra[h][e] = (kval && i < iend) ? colA[i] : 0.0;
-        const int j = j0 + ii + e;
-        double w = 0.0;
-        if (kval && j < g.r && pt != PIV_ZERO) {
-          w = colA[j] * c0;
-          if (kp != k) w = fma(colP[j], c1, w);
-        }
-        rb[h][e] = w;
+      for (int e = 0; e < RPT; ++e) {
+        const int irow = min(i0 + ii + e, rmax), jrow = min(j0 + ii + e, rmax);
+        ra[h][e] = colA[irow];
+        rb[h][e] = colA[jrow];
+        rp[h][e] = colP[jrow];
       }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < KPT; ++h)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        As[buf][kq + 8 * h][ii + e] = ra[h][e];
-        Bs[buf][kq + 8 * h][ii + e] = rb[h][e];
+      for (int e = 0; e < RPT; ++e) {
+        const bool iv = kv[h] && (i0 + ii + e < iend);
+        const bool jv = kv[h] && (j0 + ii + e < g.r);
+        As[buf][kq + KSTEP * h][ii + e] = iv ? ra[h][e] : 0.0;
+        Bs[buf][kq + KSTEP * h][ii + e] = jv ? fma(rp[h][e], c1[h], rb[h][e] * c0[h]) : 0.0;
       }
   };
 
@@ -140,7 +153,7 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_f64_kernel(SchurArgs g) {
     const int buf = kc & 1;
     if (kc + 1 < nk) load(kc + 1);
 #pragma unroll
-    for (int ks = 0; ks < SC_BK; ks += 4) {
+    for (int ks = 0; ks < BK; ks += 4) {
       double af[4], bf[4];
 #pragma unroll
       for (int x = 0; x < 4; ++x) af[x] = As[buf][ks + lk][wm * 64 + x * 16 + lrow];
@@ -171,7 +184,8 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_f64_kernel(SchurArgs g) {
 }
 
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
-                 const int* nelim, int row0, int nrows, double* s, int lds, hipStream_t stream) {
+                 const int* nelim, int row0, int nrows, double* s, int lds, int tile,
+                 hipStream_t stream) {
   SchurArgs g;
   g.r = n - p;
   g.p = p;
@@ -189,7 +203,9 @@ int launch_schur(int n, int p, const double* a, int lda, const int* piv, const d
   const int total = g.ntm * g.ntn;
   if (total == 0) return 0;
   g.per_xcd = (total + SC_NXCD - 1) / SC_NXCD;
-  schur_f64_kernel<<<g.per_xcd * SC_NXCD, SC_THREADS, 0, stream>>>(g);
+  const unsigned grid = g.per_xcd * SC_NXCD;
+  if (tile == 1) schur_f64_kernel<16, 2><<<grid, SC_THREADS, 0, stream>>>(g);
+  else schur_f64_kernel<16, 4><<<grid, SC_THREADS, 0, stream>>>(g);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }

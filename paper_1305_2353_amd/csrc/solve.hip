@@ -55,15 +55,31 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_rows_kernel(
     __syncthreads();
     // Stage L(:, k0..k0+7): zero on and above the diagonal and for the
     // in-block entry of a 2x2 pivot (its slot holds D(k+1,k)).
-    for (int idx = tid; idx < SOLVE_TPR * PW; idx += SOLVE_THREADS) {
-      const int kk = idx / PW, j = idx % PW;
-      const int k = k0 + kk;
-      double v = 0.0;
-      if (k < nelim && j > k && j < p) {
-        v = CM(a, j, k, lda);
-        if (j == k + 1 && piv_s[k] == PIV_2X2_FIRST) v = 0.0;
+    // All loads first (clamped, always in bounds), masks afterwards, so the
+    // loads of a chunk are in flight together.
+    constexpr int NIT = (SOLVE_TPR * PW + SOLVE_THREADS - 1) / SOLVE_THREADS;
+    constexpr int GRP = NIT < 8 ? NIT : 8;     // loads in flight per group
+#pragma unroll
+    for (int g0 = 0; g0 < NIT; g0 += GRP) {
+      double lv[GRP];
+#pragma unroll
+      for (int it = 0; it < GRP; ++it) {
+        const int idx = tid + (g0 + it) * SOLVE_THREADS;
+        const int k = min(k0 + idx / PW, p - 1);
+        const int j = min(idx % PW, p - 1);
+        lv[it] = CM(a, j, k, lda);
       }
-      Lc[kk][j] = v;
+#pragma unroll
+      for (int it = 0; it < GRP; ++it) {
+        const int idx = tid + (g0 + it) * SOLVE_THREADS;
+        if (idx < SOLVE_TPR * PW) {
+          const int kk = idx / PW, j = idx % PW;
+          const int k = k0 + kk;
+          const bool keep = k < nelim && j > k && j < p &&
+                            !(j == k + 1 && piv_s[k] == PIV_2X2_FIRST);
+          Lc[kk][j] = keep ? lv[it] : 0.0;
+        }
+      }
     }
     __syncthreads();
     double cur = 0.0;
@@ -76,12 +92,11 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_rows_kernel(
       const int k = k0 + kk;
       if (piv_s[k] == PIV_ZERO && c == kk) cur = 0.0;   // dropped column
       const double xk = __shfl(cur, kk, SOLVE_TPR);
+      // Lc holds exact zeros on and above the diagonal, so the update is
+      // applied to every column without a branch.
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int j = c + SOLVE_TPR * q;
-        if (j > k) x[q] = fma(-xk, Lc[kk][j], x[q]);
-      }
-      if (jc > k) cur = fma(-xk, Lc[kk][jc], cur);
+      for (int q = 0; q < NC; ++q) x[q] = fma(-xk, Lc[kk][c + SOLVE_TPR * q], x[q]);
+      cur = fma(-xk, Lc[kk][jc], cur);
     }
 #pragma unroll
     for (int q = 0; q < NC; ++q)
