@@ -121,7 +121,7 @@ def main():
         f = ctp.ctp_factor_supernode(a, opts, work=work, outs=outs)
         if ev is not None:
             ev["t2"].record(stream)
-        ctp.ctp_solve_supernode(a, f, opts)
+        ctp.ctp_solve_supernode(a, f, opts, work=work)
         if ev is not None:
             ev["t3"].record(stream)
         for bi, (row0, nr) in enumerate(blocks):

@@ -139,12 +139,15 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
  * a compressed or restricted rule: rows p..n-1 of a are replaced, in place,
  * by L21 = (A21 P^T)_E (D L_EE^T)^-1 in columns 0..nelim-1 and by the
  * delayed columns (A21 P^T)_d - L21 D L_dE^T in columns nelim..p-1.
- * perm, piv, d, nelim are the device outputs of the factorization.  For
+ * perm, piv, d, nelim are the device outputs of the factorization.  work:
+ * the workspace sized by ctp_workspace_size for the same n, p and method
+ * (it holds the column-permuted A21 while the panel is overwritten).  For
  * method CTP_TPP this call does nothing (the factorization already solved).
  * Requires p <= CTP_MAX_P. */
 int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm,
                         const int* piv, const double* d, const int* nelim,
-                        const ctp_opts* opts, hipStream_t stream);
+                        const ctp_opts* opts, void* work, size_t lwork,
+                        hipStream_t stream);
 
 /* Factor + Solve in one call (ctp_factor_supernode then, for the
  * compressed and restricted rules, ctp_solve_supernode). */

@@ -13,7 +13,7 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
                         double u, double small, int* perm, int* piv, double* d, int* nelim,
                         int* status, hipStream_t stream);
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                 const double* d, const int* nelim, hipStream_t stream);
+                 const double* d, const int* nelim, double* w, int ldw, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream);
@@ -39,6 +39,11 @@ Workspace workspace_layout(int n, int p, int method) {
     off = align_up(off + (size_t)p * w.relaxed_chunks * RELAXED_TOPK * 16, 256);
     w.crow_off = off;
     off = align_up(off + (size_t)p * sizeof(int), 256);
+  }
+  if (method != CTP_TPP && r > 0) {
+    w.ldw = (int)align_up((size_t)r, 32);
+    w.w_off = off;
+    off = align_up(off + (size_t)w.ldw * p * sizeof(double), 256);
   }
   w.misc_off = off;
   off = align_up(off + 64 * sizeof(int), 256);
@@ -144,8 +149,8 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
 }
 
 int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                        const double* d, const int* nelim, const ctp_opts* opts,
-                        hipStream_t stream) {
+                        const double* d, const int* nelim, const ctp_opts* opts, void* work,
+                        size_t lwork, hipStream_t stream) {
   if (n < p) return -1;
   if (p < 0 || p > CTP_MAX_P) return -2;
   if (!a && n > 0 && p > 0) return -3;
@@ -156,7 +161,10 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const
   if (!nelim) return -8;
   if (check_opts(opts)) return -9;
   if (opts->method == CTP_TPP) return 0;
-  return launch_solve(n, p, a, lda, perm, piv, d, nelim, stream);
+  Workspace ws = workspace_layout(n, p, opts->method);
+  if (!work || lwork < ws.total) return -11;
+  double* w = reinterpret_cast<double*>(static_cast<unsigned char*>(work) + ws.w_off);
+  return launch_solve(n, p, a, lda, perm, piv, d, nelim, w, ws.ldw, stream);
 }
 
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
@@ -164,7 +172,7 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* p
   int rc = ctp_factor_supernode(n, p, a, lda, opts, perm, piv, d, nelim, status, work, lwork, stream);
   if (rc) return rc;
   if (opts->method == CTP_TPP) return 0;
-  return ctp_solve_supernode(n, p, a, lda, perm, piv, d, nelim, opts, stream);
+  return ctp_solve_supernode(n, p, a, lda, perm, piv, d, nelim, opts, work, lwork, stream);
 }
 
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,

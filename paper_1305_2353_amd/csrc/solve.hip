@@ -1,164 +1,191 @@
 // Solve task on the column-permuted A21 (Section 1; Fig. 4.1 (d)-(e)).
 //
-// Each row of A21 is independent: with x = row of A21 P^T,
+// Every row of A21 is independent: with x = row of A21 P^T,
 //     W_E  = x_E (L_EE^T)^-1          (forward substitution, L unit lower)
 //     x_d' = x_d - W_E L_dE^T         (delayed columns)
 //     L21  = W_E D^-1                 (1x1 and 2x2 blocks)
-// so one sweep over k = 0..nelim-1 of "x_j -= x_k L(j,k) for j > k" over
-// all p columns yields W_E and the delayed columns together.
 //
-// Mapping: 8 threads per row, thread c of a row owns columns c, c+8, ...
-// in registers (NC = ceil(p/8) of them), 32 rows per workgroup.  Columns
-// of L are staged in LDS eight at a time; the pivot value x_k is broadcast
-// inside the row's 8 lanes.  The permutation is applied as a gather when
-// the row is loaded (no data movement); all loads of a workgroup finish
-// before any store, so the update is in place.
+// Two kernels:
+//  1. gather: W = A21 P^T column by column into the workspace (the
+//     permutation is applied once, as a copy; the panel can then be
+//     overwritten in place without losing original columns);
+//  2. blocked left-looking triangular solve on the matrix cores.  One wave
+//     owns 16 rows and walks the p columns in blocks of 16:
+//        X_b = W_b - W_{<b} L_{b,<b}^T        (v_mfma_f64_16x16x4, K = 16b)
+//        forward substitution inside the 16 x 16 diagonal block of L
+//        (pivot values broadcast across the lanes that hold a row);
+//     the solved block goes back to the workspace (the A operand of later
+//     blocks) and, multiplied by D^-1, to the panel as L21.  A 2x2 pivot
+//     that straddles two blocks is finished when the second block is done.
+//  Delayed columns (positions >= nelim) receive the GEMM and in-block
+//  updates from every eliminated column and are written unscaled.
 
 #include "common.h"
 
 namespace ctp {
 
-constexpr int SOLVE_TPR = 8;                       // threads per row
-constexpr int SOLVE_THREADS = 256;
-constexpr int SOLVE_RPB = SOLVE_THREADS / SOLVE_TPR;  // rows per workgroup
+typedef double d4s __attribute__((ext_vector_type(4)));
 
-template <int NC>
-__global__ __launch_bounds__(SOLVE_THREADS) void solve_rows_kernel(
-    int r, int p, double* __restrict__ a, int lda, const int* __restrict__ perm,
-    const int* __restrict__ piv, const double* __restrict__ d, const int* __restrict__ nelim_p) {
-  constexpr int PW = SOLVE_TPR * NC;               // padded width
-  __shared__ double Lc[SOLVE_TPR][PW];
-  __shared__ int piv_s[PW];
-  const int tid = threadIdx.x;
-  const int c = tid % SOLVE_TPR;
-  const int row = blockIdx.x * SOLVE_RPB + tid / SOLVE_TPR;
-  const bool valid = row < r;
+constexpr int SOLVE_THREADS = 256;   // 4 waves, 16 rows each
+constexpr int SOLVE_ROWS = 64;
+
+__global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a21,
+                                                         int lda, const int* __restrict__ perm,
+                                                         double* __restrict__ w, int ldw) {
+  const int j = blockIdx.y;
+  const double* src = a21 + (size_t)perm[j] * lda;
+  double* dst = w + (size_t)j * ldw;
+  const int i0 = blockIdx.x * 4096;
+  const int i1 = min(r, i0 + 4096);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
+}
+
+// 2x2 pivot inverse entries, scaled as in the pivot search.
+CTP_DEV void inv2x2(double a11, double a21, double a22, double& i11, double& i21, double& i22) {
+  const double s = 1.0 / fmax(fmax(fabs(a11), fabs(a21)), fabs(a22));
+  const double det = (a22 * s) * a11 - (a21 * s) * a21;
+  const double f = s / det;
+  i11 = f * a22;
+  i21 = -(f * a21);
+  i22 = f * a11;
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
+    int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
+    const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw) {
+  __shared__ int piv_s[CTP_MAX_P + 32];
+  __shared__ double d_s[2 * CTP_MAX_P + 64];
+  for (int k = threadIdx.x; k < p + 32; k += SOLVE_THREADS) {
+    piv_s[k] = k < p ? piv[k] : PIV_DELAYED;
+    d_s[2 * k] = k < p ? d[2 * k] : 0.0;
+    d_s[2 * k + 1] = k < p ? d[2 * k + 1] : 0.0;
+  }
+  __syncthreads();
+
   const int nelim = min(max(*nelim_p, 0), p);
+  const int lane = threadIdx.x & 63;
+  const int r0 = (blockIdx.x * SOLVE_THREADS + threadIdx.x) / 64 * 16;   // first row of this wave
+  if (r0 >= r) return;
   double* a21 = a + p;
-
-  for (int j = tid; j < PW; j += SOLVE_THREADS) piv_s[j] = j < p ? piv[j] : PIV_DELAYED;
-
-  double x[NC];
+  const int ga = lane >> 4;          // accumulator rows ga + 4q
+  const int c = lane & 15;           // accumulator column
+  const int fr = lane & 15;          // fragment row (A operand) / column (B operand)
+  const int fk = lane >> 4;          // fragment k
+  const int rmax = r - 1;
+  const int arow = min(r0 + fr, rmax);
+  int rows[4];
+  bool rv[4];
 #pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const int j = c + SOLVE_TPR * q;
-    x[q] = (valid && j < p) ? a21[(size_t)perm[j] * lda + row] : 0.0;
+  for (int q = 0; q < 4; ++q) {
+    rows[q] = r0 + ga + 4 * q;
+    rv[q] = rows[q] < r;
+    rows[q] = min(rows[q], rmax);
   }
 
-  // Chunks of 8 pivot columns.  The register holding the chunk's own
-  // columns is selected once into `cur` (the chunk index is not a
-  // compile-time constant), updated there, and written back at the end.
-#pragma unroll 1
-  for (int kb = 0; kb < NC; ++kb) {
-    const int k0 = kb * SOLVE_TPR;
-    if (k0 >= nelim) break;
-    __syncthreads();
-    // Stage L(:, k0..k0+7): zero on and above the diagonal and for the
-    // in-block entry of a 2x2 pivot (its slot holds D(k+1,k)).
-    // All loads first (clamped, always in bounds), masks afterwards, so the
-    // loads of a chunk are in flight together.
-    constexpr int NIT = (SOLVE_TPR * PW + SOLVE_THREADS - 1) / SOLVE_THREADS;
-    constexpr int GRP = NIT < 8 ? NIT : 8;     // loads in flight per group
+  const int nb = (p + 15) / 16;
+  double carry[4] = {0.0, 0.0, 0.0, 0.0};   // previous block's column 15 (lanes c == 15)
+  for (int b = 0; b < nb; ++b) {
+    const int j0 = 16 * b;
+    const int jc = j0 + c;                   // this lane's column
+    const bool cv = jc < p;
+    const int jcc = min(jc, p - 1);
+    d4s acc;
 #pragma unroll
-    for (int g0 = 0; g0 < NIT; g0 += GRP) {
-      double lv[GRP];
+    for (int q = 0; q < 4; ++q) acc[q] = w[(size_t)jcc * ldw + rows[q]];
+
+    // X_b -= W_{<b} L_{b,<b}^T over the eliminated columns k < min(j0, nelim)
+    const int kend = min(j0, nelim);
+    const int bj = min(j0 + fr, p - 1);      // B operand: row j0+fr of L
+    for (int k0 = 0; k0 < kend; k0 += 4) {
+      const int k = k0 + fk;
+      const bool kv = k < kend;
+      const int kc = kv ? k : 0;
+      double af = w[(size_t)kc * ldw + arow];
+      double bf = CM(a, bj, kc, lda);
+      // L(j0, j0-1) is the in-block entry of a 2x2 pivot straddling the
+      // block boundary: it holds D, not L.
+      const bool straddle = (j0 + fr == k + 1) && piv_s[kc] == PIV_2X2_FIRST;
+      af = kv ? -af : 0.0;
+      bf = (kv && !straddle && j0 + fr < p) ? bf : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
+    }
+
+    // forward substitution inside the block
+    const int kkend = min(16, nelim - j0);
+    for (int kk = 0; kk < kkend; ++kk) {
+      const int k = j0 + kk;
+      double lv = CM(a, jcc, k, lda);
+      const bool keep = cv && c > kk && !(c == kk + 1 && piv_s[k] == PIV_2X2_FIRST);
+      lv = keep ? lv : 0.0;
+      if (piv_s[k] == PIV_ZERO && c == kk) {
 #pragma unroll
-      for (int it = 0; it < GRP; ++it) {
-        const int idx = tid + (g0 + it) * SOLVE_THREADS;
-        const int k = min(k0 + idx / PW, p - 1);
-        const int j = min(idx % PW, p - 1);
-        lv[it] = CM(a, j, k, lda);
+        for (int q = 0; q < 4; ++q) acc[q] = 0.0;
+      }
+      const int src = (lane & 48) | kk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double xk = __shfl(acc[q], src, 64);
+        acc[q] = fma(-xk, lv, acc[q]);
+      }
+    }
+
+    // solved block -> workspace (A operand of later blocks)
+    if (cv && jc < nelim) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (rv[q]) w[(size_t)jc * ldw + rows[q]] = acc[q];
+    }
+    __threadfence_block();
+
+    // outputs: L21 = W D^-1 for eliminated columns, raw for delayed ones
+    const int pt = piv_s[jcc];
+    double nxt[4], prv[4], prevc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      nxt[q] = __shfl(acc[q], (lane + 1) & 63, 64);
+      prv[q] = __shfl(acc[q], (lane + 63) & 63, 64);
+      prevc[q] = __shfl(carry[q], (lane & 48) | 15, 64);
+    }
+    if (cv) {
+      double i11 = 0.0, i21 = 0.0, i22 = 0.0;
+      if (jc < nelim && (pt == PIV_2X2_FIRST || pt == PIV_2X2_SECOND)) {
+        const int k = pt == PIV_2X2_FIRST ? jc : jc - 1;
+        inv2x2(d_s[2 * k], d_s[2 * k + 1], d_s[2 * k + 2], i11, i21, i22);
       }
 #pragma unroll
-      for (int it = 0; it < GRP; ++it) {
-        const int idx = tid + (g0 + it) * SOLVE_THREADS;
-        if (idx < SOLVE_TPR * PW) {
-          const int kk = idx / PW, j = idx % PW;
-          const int k = k0 + kk;
-          const bool keep = k < nelim && j > k && j < p &&
-                            !(j == k + 1 && piv_s[k] == PIV_2X2_FIRST);
-          Lc[kk][j] = keep ? lv[it] : 0.0;
+      for (int q = 0; q < 4; ++q) {
+        if (!rv[q]) continue;
+        double* rowp = a21 + rows[q];
+        if (jc >= nelim) {
+          rowp[(size_t)jc * lda] = acc[q];
+        } else if (pt == PIV_1X1) {
+          rowp[(size_t)jc * lda] = acc[q] / d_s[2 * jc];
+        } else if (pt == PIV_ZERO) {
+          rowp[(size_t)jc * lda] = 0.0;
+        } else if (pt == PIV_2X2_FIRST) {
+          if (c < 15) rowp[(size_t)jc * lda] = acc[q] * i11 + nxt[q] * i21;
+          // c == 15: finished with the next block
+        } else {
+          const double w1 = c > 0 ? prv[q] : prevc[q];
+          const double w2 = acc[q];
+          rowp[(size_t)jc * lda] = w1 * i21 + w2 * i22;
+          if (c == 0) rowp[(size_t)(jc - 1) * lda] = w1 * i11 + w2 * i21;
         }
       }
     }
-    __syncthreads();
-    double cur = 0.0;
 #pragma unroll
-    for (int q = 0; q < NC; ++q)
-      if (q == kb) cur = x[q];
-    const int jc = c + k0;
-    const int kend = min(SOLVE_TPR, nelim - k0);
-    for (int kk = 0; kk < kend; ++kk) {
-      const int k = k0 + kk;
-      if (piv_s[k] == PIV_ZERO && c == kk) cur = 0.0;   // dropped column
-      const double xk = __shfl(cur, kk, SOLVE_TPR);
-      // Lc holds exact zeros on and above the diagonal, so the update is
-      // applied to every column without a branch.
-#pragma unroll
-      for (int q = 0; q < NC; ++q) x[q] = fma(-xk, Lc[kk][c + SOLVE_TPR * q], x[q]);
-      cur = fma(-xk, Lc[kk][jc], cur);
-    }
-#pragma unroll
-    for (int q = 0; q < NC; ++q)
-      if (q == kb) x[q] = cur;
-  }
-
-  // L21 = W D^-1.  A 2x2 block needs the neighbouring column, which lives
-  // in the next (previous) lane, or in the register after (before) it for
-  // the last (first) lane of the row's group.
-  double carry = 0.0;   // W value of column j-1 before it was overwritten
-#pragma unroll
-  for (int q = 0; q < NC; ++q) {
-    const double nxt_src = (c == 0) ? (q + 1 < NC ? x[q + 1] : 0.0) : x[q];
-    const double prv_src = (c == SOLVE_TPR - 1) ? carry : x[q];
-    const double nxt = __shfl(nxt_src, (c + 1) % SOLVE_TPR, SOLVE_TPR);
-    const double prv = __shfl(prv_src, (c + SOLVE_TPR - 1) % SOLVE_TPR, SOLVE_TPR);
-    const int j = c + SOLVE_TPR * q;
-    double v = x[q];
-    if (j < nelim) {
-      const int pt = piv_s[j];
-      if (pt == PIV_1X1) {
-        v = x[q] / d[2 * j];
-      } else if (pt == PIV_ZERO) {
-        v = 0.0;
-      } else {
-        const int k = (pt == PIV_2X2_FIRST) ? j : j - 1;
-        const double a11 = d[2 * k], a21 = d[2 * k + 1], a22 = d[2 * k + 2];
-        const double s = 1.0 / fmax(fmax(fabs(a11), fabs(a21)), fabs(a22));
-        const double det = (a22 * s) * a11 - (a21 * s) * a21;
-        const double f = s / det;
-        const double i11 = f * a22, i21 = -(f * a21), i22 = f * a11;
-        const double w1 = (pt == PIV_2X2_FIRST) ? x[q] : prv;
-        const double w2 = (pt == PIV_2X2_FIRST) ? nxt : x[q];
-        v = (pt == PIV_2X2_FIRST) ? (w1 * i11 + w2 * i21) : (w1 * i21 + w2 * i22);
-      }
-    }
-    carry = x[q];
-    x[q] = v;
-  }
-  __syncthreads();   // every gather load of this workgroup is done
-  if (valid) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const int j = c + SOLVE_TPR * q;
-      if (j < p) a21[(size_t)j * lda + row] = x[q];
-    }
+    for (int q = 0; q < 4; ++q) carry[q] = acc[q];
   }
 }
 
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                 const double* d, const int* nelim, hipStream_t stream) {
+                 const double* d, const int* nelim, double* w, int ldw, hipStream_t stream) {
   const int r = n - p;
   if (r <= 0 || p <= 0) return 0;
-  const int nc = (p + SOLVE_TPR - 1) / SOLVE_TPR;
-  dim3 grid((r + SOLVE_RPB - 1) / SOLVE_RPB);
-#define CTP_SOLVE_CASE(NCV)                                                                    \
-  if (nc <= NCV) {                                                                             \
-    solve_rows_kernel<NCV><<<grid, SOLVE_THREADS, 0, stream>>>(r, p, a, lda, perm, piv, d, nelim); \
-  } else
-  CTP_SOLVE_CASE(1) CTP_SOLVE_CASE(2) CTP_SOLVE_CASE(4) CTP_SOLVE_CASE(8) CTP_SOLVE_CASE(16)
-  CTP_SOLVE_CASE(32) CTP_SOLVE_CASE(64) { return -2; }
-#undef CTP_SOLVE_CASE
+  dim3 gg((r + 4095) / 4096, p);
+  solve_gather_kernel<<<gg, 256, 0, stream>>>(r, p, a + p, lda, perm, w, ldw);
+  solve_mfma_kernel<<<(r + SOLVE_ROWS - 1) / SOLVE_ROWS, SOLVE_THREADS, 0, stream>>>(r, p, a, lda, piv, d,
+                                                                                 nelim, w, ldw);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }

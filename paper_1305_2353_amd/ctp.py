@@ -58,7 +58,7 @@ def load(path=LIB_PATH):
         "ctp_workspace_size": (I, [I, I, OPT, ctypes.POINTER(SZ)]),
         "ctp_compress": (I, [I, I, P, I, I, P, I, P, P, P, SZ, P]),
         "ctp_factor_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
-        "ctp_solve_supernode": (I, [I, I, P, I, P, P, P, P, OPT, P]),
+        "ctp_solve_supernode": (I, [I, I, P, I, P, P, P, P, OPT, P, SZ, P]),
         "ctp_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
         "ctp_schur": (I, [I, I, P, I, P, P, P, I, I, P, I, OPT, P]),
     }
@@ -162,10 +162,12 @@ def ctp_factor_supernode(a, opts, work=None, outs=None):
     return {"perm": perm[:p], "piv": piv[:p], "d": d[:2 * p], "nelim": nelim, "status": status}
 
 
-def ctp_solve_supernode(a, f, opts):
+def ctp_solve_supernode(a, f, opts, work=None):
     n, p, lda = _panel_args(a)
+    work = work if work is not None else workspace(n, p, opts, a.device)
     _check(load().ctp_solve_supernode(n, p, _ptr(a), lda, _ptr(f["perm"]), _ptr(f["piv"]), _ptr(f["d"]),
-                                      _ptr(f["nelim"]), ctypes.byref(opts), _stream()),
+                                      _ptr(f["nelim"]), ctypes.byref(opts), _ptr(work), work.numel(),
+                                      _stream()),
            "ctp_solve_supernode")
 
 

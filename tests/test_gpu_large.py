@@ -35,8 +35,9 @@ def test_full_size_supernode(panel, method):
     a = ctp.device_panel(A)
     C, crow, _ = ctp.ctp_compress(a, p, method)
     opts = ctp.ctp_default_opts(method)
-    f = ctp.ctp_factor_supernode(a, opts)
-    ctp.ctp_solve_supernode(a, f, opts)
+    work = ctp.workspace(n, p, opts)
+    f = ctp.ctp_factor_supernode(a, opts, work=work)
+    ctp.ctp_solve_supernode(a, f, opts, work=work)
     torch.cuda.synchronize()
 
     # compression: exact
