@@ -34,6 +34,25 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 matrix
 PEAK_HBM_GBS = 8000.0
 BLOCK_ROWS = 4096
 
+# HBM bytes per Form launch from two rocprofv3 --pmc runs (FETCH_SIZE scaled by
+# the 1.9997 read factor measured on a plain copy of known size, WRITE_SIZE
+# unscaled), valid only for the kernel source they were measured on.
+FORM_COUNTERS = {
+    "source_sha256": "325da8befa20b8d5350ed44df31eba985a48bb3b19a093e033e18c58768bd152",
+    "hbm_bytes_per_launch": 2.372e9 + 1.584e9,
+    "n": 100000, "p": 512,
+}
+
+
+def form_traffic(n, p):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1305_2353_amd", "csrc", "schur.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    c = FORM_COUNTERS
+    if sha != c["source_sha256"] or (n, p) != (c["n"], c["p"]):
+        return None
+    return c["hbm_bytes_per_launch"]
+
 
 def algorithmic_flops(n, p, nelim):
     r = n - p
@@ -189,7 +208,8 @@ def main():
                    "delayed": p - nelim, "status": status},
         "roofline": {"bound": "mfma", "kernel": "schur_f64_kernel", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": None, "avg_launch_ms": round(avg_launch_ms, 4), "launches_per_step": launches},
+                     "traffic": form_traffic(n, p), "avg_launch_ms": round(avg_launch_ms, 4),
+                     "launches_per_step": launches},
         "phases_ms": phase,
         "algorithmic_gflop_per_step": round(flops / 1e9, 2),
     }
