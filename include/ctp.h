@@ -37,7 +37,9 @@
  *   updated by all eliminations (lower triangle) and the rows L_dE.
  *   Rows p..n-1 (A21) are never permuted: columns k < nelim hold L21 and
  *   columns k >= nelim hold the delayed columns A21_d - L21 D L_dE^T.
- *   The strict upper triangle of rows 0..p-1 is not referenced.
+ *   The strict upper triangle of rows 0..p-1 is used as working storage by
+ *   the pivot search (A11 is held there as a full square) and is
+ *   overwritten; its contents on return are unspecified.
  *   perm[k] = original column (0-based) now at position k.
  *   piv[k]  = CTP_PIV_1X1, CTP_PIV_2X2_FIRST / CTP_PIV_2X2_SECOND (the two
  *             positions of a 2x2 pivot), CTP_PIV_ZERO (a column whose
@@ -129,8 +131,10 @@ int ctp_compress(int n, int p, const double* a, int lda, int method,
  *   RESTRICTED: A11 alone.
  * perm[p], piv[p], d[2p], nelim[1], status[1]: device outputs (status is
  * cleared first).  work: device workspace of lwork >= ctp_workspace_size
- * bytes.  TPP panels with p > CTP_MAX_P or more than 2048 rows in A21 are
- * accepted but run on a single workgroup (intended for small panels). */
+ * bytes.  Requires p <= CTP_MAX_P.  The pivot search is enqueued as a fixed
+ * sequence of kernels (batches of up to 8 eliminated columns are applied to
+ * the trailing matrix by a grid-wide kernel), so the call stays
+ * graph-capturable whatever the data. */
 int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
                          int* perm, int* piv, double* d, int* nelim, int* status,
                          void* work, size_t lwork, hipStream_t stream);

@@ -63,10 +63,15 @@ text and nothing else:
                    l_i1 = w_i1*Dinv11 + w_i2*Dinv21,  l_i2 = w_i1*Dinv12 + w_i2*Dinv22
                    a_ij <- a_ij - (l_i1*w_j1 + l_i2*w_j2)
 
-Storage.  A11 is held as a full symmetric matrix.  Only its lower triangle
-(row index >= column index) is ever computed; after each update the upper
-triangle is refreshed as the mirror image, so that the symmetric
-interchanges are plain row-and-column swaps.
+Storage.  A11 is held as a full square (its lower triangle reflected at the
+start).  Each elimination updates the whole trailing square with the plain
+outer product above, both triangles independently, so entry (i, j) always
+receives l_i * w_j; the two triangles may therefore differ in the last bit.
+The symmetric interchanges are plain row-and-column swaps of the square.
+Reads follow the paper's notation: a column is read down the square (entries
+above and below the diagonal of column m), the partner search reads row m
+left of the diagonal, and pivot blocks use the diagonal and the entry below
+it.  The factors are the lower triangle.
 
 Numbers may be numpy float64 arrays or numpy object arrays of
 fractions.Fraction (exact rational mode); the code is the same for both.
@@ -139,10 +144,10 @@ class Decision:
 class TrapezoidFactors:
     """Result of threshold pivoting on [A11; R] (final positions).
 
-    T:     p x p, lower triangle holds the factors: for eliminated column k,
+    T:     p x p square; its lower triangle holds the factors: for eliminated column k,
            T[k,k] = D(k,k), T[k+1,k] = D(k+1,k) when k starts a 2x2 pivot,
            other entries below the diagonal are L; the delayed block holds the
-           updated A11 entries.  Upper triangle: unspecified.
+           updated A11 entries.  Upper triangle: working values.
     R:     r x p, eliminated columns hold L rows of R (TPP / relaxed) or the
            bound on them (strict); delayed columns hold the updated R.
     perm:  perm[k] = original column at final position k.
@@ -220,20 +225,12 @@ def _swap(T, R, perm, a, b):
     perm[[a, b]] = perm[[b, a]]
 
 
-def _mirror_block(T, k0):
-    """Refresh the upper triangle of the trailing block T[k0:, k0:] from its
-    lower triangle."""
-    blk = T[k0:, k0:]
-    T[k0:, k0:] = np.tril(blk) + np.tril(blk, -1).T
-
-
 def _eliminate_1x1(T, R, k, r_update):
     """Apply the 1x1 pivot at position k to the trailing trapezoid."""
     d = T[k, k]
     w = T[k + 1:, k].copy()             # column below the pivot (A11 rows)
     l = w / d
     T[k + 1:, k + 1:] = T[k + 1:, k + 1:] - np.outer(l, w)
-    _mirror_block(T, k + 1)
     T[k + 1:, k] = l
     if r_update == R_NORMAL:
         wr = R[:, k].copy()
@@ -260,7 +257,6 @@ def _eliminate_2x2(T, R, k, r_update):
     l1 = w1 * i11 + w2 * i21
     l2 = w1 * i21 + w2 * i22
     T[k + 2:, k + 2:] = T[k + 2:, k + 2:] - (np.outer(l1, w1) + np.outer(l2, w2))
-    _mirror_block(T, k + 2)
     T[k + 2:, k] = l1
     T[k + 2:, k + 1] = l2
     if r_update == R_NORMAL:

@@ -11,7 +11,7 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
                     int* crow, int* status, void* work, hipStream_t stream);
 int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, int abs_update,
                         double u, double small, int* perm, int* piv, double* d, int* nelim,
-                        int* status, hipStream_t stream);
+                        int* status, void* state, double* wbuf, hipStream_t stream);
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
                  const double* d, const int* nelim, double* w, int ldw, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
@@ -40,6 +40,10 @@ Workspace workspace_layout(int n, int p, int method) {
     w.crow_off = off;
     off = align_up(off + (size_t)p * sizeof(int), 256);
   }
+  w.st_off = off;
+  off = align_up(off + (size_t)pivot_state_bytes(), 256);
+  w.wb_off = off;
+  off = align_up(off + pivot_wbuf_bytes(p), 256);
   if (method != CTP_TPP && r > 0) {
     w.ldw = (int)align_up((size_t)r, 32);
     w.w_off = off;
@@ -110,7 +114,7 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
                          double* d, int* nelim, int* status, void* work, size_t lwork,
                          hipStream_t stream) {
   if (n < p) return -1;
-  if (p < 0 || p > 4096) return -2;
+  if (p < 0) return -2;
   if (!a && n > 0 && p > 0) return -3;
   if (lda < (n > 1 ? n : 1)) return -4;
   if (check_opts(opts)) return -5;
@@ -122,7 +126,7 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
   const int method = opts->method;
   Workspace ws = workspace_layout(n, p, method);
   if (!work || lwork < ws.total) return -12;
-  if ((method == CTP_STRICT || method == CTP_RELAXED) && p > CTP_MAX_P) return -2;
+  if (p > CTP_MAX_P) return -2;
 
   clear_status_kernel<<<1, 1, 0, stream>>>(status);
   unsigned char* base = static_cast<unsigned char*>(work);
@@ -145,7 +149,8 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
     rrows = r;
   }
   return launch_pivot_factor(p, a, lda, rrows, R, ldr, abs_update, opts->u, opts->small, perm, piv,
-                             d, nelim, status, stream);
+                             d, nelim, status, base + ws.st_off,
+                             reinterpret_cast<double*>(base + ws.wb_off), stream);
 }
 
 int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const int* piv,

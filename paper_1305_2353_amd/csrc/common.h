@@ -47,6 +47,8 @@ struct Workspace {
   size_t j_off = 0;       // (n-p) ints: strict row -> set, relaxed scratch
   size_t cand_off = 0;    // relaxed: per-chunk candidate keys
   size_t crow_off = 0;    // relaxed: p ints, A21 row behind each C row
+  size_t st_off = 0;      // pivot-search state carried between launches
+  size_t wb_off = 0;      // pivot-search batch of pivot-column values
   size_t w_off = 0;       // compressed / restricted: (n-p) x p doubles, solve gather buffer
   int ldw = 1;
   size_t misc_off = 0;    // 64 ints of counters / flags
@@ -55,6 +57,8 @@ struct Workspace {
 };
 
 int relaxed_chunk_count(int rows);
+int pivot_state_bytes();
+size_t pivot_wbuf_bytes(int p);
 Workspace workspace_layout(int n, int p, int method);
 
 }  // namespace ctp
