@@ -4,7 +4,8 @@ One step (all on the GPU, inputs resident in HBM):
     stage    copy the pristine panel into the working panel (in-place method)
     factor   compression of A21 + pivot search on [A11; C]   (ctp_factor_supernode)
     solve    L21 and the delayed columns                      (ctp_solve_supernode)
-    form     S = L21 D L21^T, lower triangle, in 4096-row blocks written to
+    form     S = L21 D L21^T = L21 W^T from the W = L21 D the solve left in
+             the workspace, lower triangle, in 4096-row blocks written to
              one reused block buffer                          (ctp_schur x 25)
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--method relaxed]
@@ -38,8 +39,8 @@ BLOCK_ROWS = 4096
 # the 1.9997 read factor measured on a plain copy of known size, WRITE_SIZE
 # unscaled), valid only for the kernel source they were measured on.
 FORM_COUNTERS = {
-    "source_sha256": "325da8befa20b8d5350ed44df31eba985a48bb3b19a093e033e18c58768bd152",
-    "hbm_bytes_per_launch": 2.372e9 + 1.584e9,
+    "source_sha256": None,
+    "hbm_bytes_per_launch": None,
     "n": 100000, "p": 512,
 }
 
@@ -96,7 +97,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--method", default="relaxed", choices=["relaxed", "strict", "restricted"])
+    ap.add_argument("--method", default="relaxed", choices=["relaxed", "strict", "restricted", "tpp"])
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--p", type=int, default=512)
     ap.add_argument("--seed", type=int, default=0)
@@ -146,7 +147,7 @@ def main():
         for bi, (row0, nr) in enumerate(blocks):
             if ev is not None:
                 ev["s"][bi][0].record(stream)
-            ctp.ctp_schur(a, f, row0, nr, opts, s=S[:nr, :row0 + nr])
+            ctp.ctp_schur(a, f, row0, nr, opts, s=S[:nr, :row0 + nr], work=work)
             if ev is not None:
                 ev["s"][bi][1].record(stream)
         if ev is not None:
@@ -206,7 +207,7 @@ def main():
                                f"Factor+Solve+Form, S in {BLOCK_ROWS}-row blocks",
                    "n": n, "p": p, "method": args.method, "seed": args.seed, "nelim": nelim,
                    "delayed": p - nelim, "status": status},
-        "roofline": {"bound": "mfma", "kernel": "schur_f64_kernel", "achieved": round(achieved, 3),
+        "roofline": {"bound": "mfma", "kernel": "schur_w_kernel", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "traffic": form_traffic(n, p), "avg_launch_ms": round(avg_launch_ms, 4),
                      "launches_per_step": launches},
@@ -224,6 +225,7 @@ def main():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         tf = ctp.ctp_factor_supernode(a, topts, work=tw, outs=tout)
+        ctp.ctp_solve_supernode(a, tf, topts, work=tw)      # W = L21 D for the Form
         e1.record(stream)
         torch.cuda.synchronize()
         tpp_ms = e0.elapsed_time(e1)

@@ -139,22 +139,25 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
                          int* perm, int* piv, double* d, int* nelim, int* status,
                          void* work, size_t lwork, hipStream_t stream);
 
-/* Solve task (Section 1; Fig. 4.1 (d)-(e)) after ctp_factor_supernode with
- * a compressed or restricted rule: rows p..n-1 of a are replaced, in place,
+/* Solve task (Section 1; Fig. 4.1 (d)-(e)) after ctp_factor_supernode.
+ * Compressed and restricted rules: rows p..n-1 of a are replaced, in place,
  * by L21 = (A21 P^T)_E (D L_EE^T)^-1 in columns 0..nelim-1 and by the
  * delayed columns (A21 P^T)_d - L21 D L_dE^T in columns nelim..p-1.
+ * Threshold partial pivoting (CTP_TPP): the factorization already produced
+ * L21 and the panel is left as it is.
+ * For every rule the call also leaves W = L21 D (n-p rows, nelim columns)
+ * in the workspace, the second operand of the Form task (ctp_schur).
  * perm, piv, d, nelim are the device outputs of the factorization.  work:
  * the workspace sized by ctp_workspace_size for the same n, p and method
- * (it holds the column-permuted A21 while the panel is overwritten).  For
- * method CTP_TPP this call does nothing (the factorization already solved).
+ * (it also holds the column-permuted A21 while the panel is overwritten).
  * Requires p <= CTP_MAX_P. */
 int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm,
                         const int* piv, const double* d, const int* nelim,
                         const ctp_opts* opts, void* work, size_t lwork,
                         hipStream_t stream);
 
-/* Factor + Solve in one call (ctp_factor_supernode then, for the
- * compressed and restricted rules, ctp_solve_supernode). */
+/* Factor + Solve in one call (ctp_factor_supernode then
+ * ctp_solve_supernode, for every rule). */
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
                   int* perm, int* piv, double* d, int* nelim, int* status,
                   void* work, size_t lwork, hipStream_t stream);
@@ -164,10 +167,16 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
  * (i, j), j <= i, is written to s[(i-row0) + j*lds]; s holds nrows rows and
  * row0+nrows columns, lds >= nrows; entries above the diagonal are not
  * written.  a, piv, d, nelim as returned by the factorization (L21 in rows
- * p..n-1, columns 0..nelim-1).  FP64 matrix-core arithmetic. */
+ * p..n-1, columns 0..nelim-1).
+ * work / lwork: either the workspace that ctp_solve_supernode (or
+ * ctp_supernode) filled for this panel, unchanged since, with lwork >=
+ * ctp_workspace_size; then S = L21 W^T is formed from the stored W = L21 D
+ * (the fast path).  Or work = NULL: W is formed from L21, piv and d inside
+ * the kernel.  Errors: -14 when work is given and lwork is too small.
+ * FP64 matrix-core arithmetic. */
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
               const int* nelim, int row0, int nrows, double* s, int lds,
-              const ctp_opts* opts, hipStream_t stream);
+              const ctp_opts* opts, const void* work, size_t lwork, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,10 @@ int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* p
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream);
+int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int ldw,
+                   const int* nelim, int row0, int nrows, double* s, int lds, hipStream_t stream);
+int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
+                  const int* nelim, double* w, int ldw, hipStream_t stream);
 
 __global__ void clear_status_kernel(int* status) { *status = 0; }
 
@@ -44,7 +48,7 @@ Workspace workspace_layout(int n, int p, int method) {
   off = align_up(off + (size_t)pivot_state_bytes(), 256);
   w.wb_off = off;
   off = align_up(off + pivot_wbuf_bytes(p), 256);
-  if (method != CTP_TPP && r > 0) {
+  if (r > 0) {
     w.ldw = (int)align_up((size_t)r, 32);
     w.w_off = off;
     off = align_up(off + (size_t)w.ldw * p * sizeof(double), 256);
@@ -165,10 +169,10 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const
   if (!d && p > 0) return -7;
   if (!nelim) return -8;
   if (check_opts(opts)) return -9;
-  if (opts->method == CTP_TPP) return 0;
   Workspace ws = workspace_layout(n, p, opts->method);
   if (!work || lwork < ws.total) return -11;
   double* w = reinterpret_cast<double*>(static_cast<unsigned char*>(work) + ws.w_off);
+  if (opts->method == CTP_TPP) return launch_form_w(n, p, a, lda, piv, d, nelim, w, ws.ldw, stream);
   return launch_solve(n, p, a, lda, perm, piv, d, nelim, w, ws.ldw, stream);
 }
 
@@ -176,13 +180,12 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* p
                   double* d, int* nelim, int* status, void* work, size_t lwork, hipStream_t stream) {
   int rc = ctp_factor_supernode(n, p, a, lda, opts, perm, piv, d, nelim, status, work, lwork, stream);
   if (rc) return rc;
-  if (opts->method == CTP_TPP) return 0;
   return ctp_solve_supernode(n, p, a, lda, perm, piv, d, nelim, opts, work, lwork, stream);
 }
 
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
               const int* nelim, int row0, int nrows, double* s, int lds, const ctp_opts* opts,
-              hipStream_t stream) {
+              const void* work, size_t lwork, hipStream_t stream) {
   if (n < p) return -1;
   if (p < 0 || p > CTP_MAX_P) return -2;
   if (!a && n > 0 && p > 0) return -3;
@@ -195,6 +198,14 @@ int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const doub
   if (!s && nrows > 0) return -10;
   if (lds < (nrows > 1 ? nrows : 1)) return -11;
   if (check_opts(opts)) return -12;
+  if (work) {
+    Workspace ws = workspace_layout(n, p, opts->method);
+    if (lwork < ws.total) return -14;
+    if (nrows == 0) return 0;
+    const double* w =
+        reinterpret_cast<const double*>(static_cast<const unsigned char*>(work) + ws.w_off);
+    return launch_schur_w(n, p, a, lda, w, ws.ldw, nelim, row0, nrows, s, lds, stream);
+  }
   if (nrows == 0) return 0;
   return launch_schur(n, p, a, lda, piv, d, nelim, row0, nrows, s, lds, opts->tile, stream);
 }

@@ -183,6 +183,204 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_f64_kernel(SchurArgs g) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// Form from an explicit W = L21 D (the Solve leaves it in its workspace):
+// S = L21 W^T is then a plain product of two row panels, so staging is two
+// streams of raw values with no pivot lookups, no D arithmetic and no
+// per-element masks.  Same 128 x 128 tiling, wave layout and tile order as
+// above.  A thread stages 4 consecutive rows of one k column per operand;
+// with VEC the 4 values come in as two 16-byte loads (needs 16-byte aligned
+// columns).  Rows past the end are never masked: their products land only
+// in rows / columns of the tile that the epilogue discards, so it is enough
+// that their addresses stay inside the arrays (a group that straddles the
+// last row falls back to clamped scalar loads).  Columns k >= nelim of the
+// last chunk are read from column nelim-1 and zeroed.
+// ---------------------------------------------------------------------------
+
+struct SchurWArgs {
+  int r;
+  const double* l21;   // a + p
+  int lda;
+  const double* w;     // W = L21 D, r x nelim, column-major
+  int ldw;
+  const int* nelim_p;
+  int p;
+  int row0, nrows;
+  double* s;
+  int lds;
+  int ntm, ntn;
+  int per_xcd;
+};
+
+// Main loop and epilogue of one tile.  VEC: every row of both operands
+// that this tile stages exists and each column is 16-byte aligned, so a
+// thread's 4 rows come in as two 16-byte loads; otherwise 4 clamped loads.
+template <bool VEC>
+__device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0, int K,
+                                             double (*As)[16][SC_BM], double (*Bs)[16][SC_BN]) {
+  constexpr int BK = 16;
+  constexpr int RPT = 4;
+  constexpr int TPK = SC_BM / RPT;          // 32 threads per k column
+  constexpr int KSTEP = SC_THREADS / TPK;   // 8 k columns at once
+  constexpr int KPT = BK / KSTEP;           // 2 k columns per thread
+  const int iend = g.row0 + g.nrows;
+  const int nk = (K + BK - 1) / BK;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int ii = (tid % TPK) * RPT;
+  const int kq = tid / TPK;
+  const int ga = i0 + ii, gb = j0 + ii;
+  int rowa[RPT], rowb[RPT];
+#pragma unroll
+  for (int e = 0; e < RPT; ++e) {
+    rowa[e] = VEC ? ga + e : min(ga + e, g.r - 1);
+    rowb[e] = VEC ? gb + e : min(gb + e, g.r - 1);
+  }
+
+  double ra[KPT][RPT], rb[KPT][RPT];
+  bool kv[KPT];
+  auto load = [&](int kc) {
+#pragma unroll
+    for (int h = 0; h < KPT; ++h) {
+      const int k = kc * BK + kq + KSTEP * h;
+      kv[h] = k < K;
+      const int kk = min(k, K - 1);
+      const double* ca = g.l21 + (size_t)kk * g.lda;
+      const double* cb = g.w + (size_t)kk * g.ldw;
+      if (VEC) {
+        const double2 x0 = *reinterpret_cast<const double2*>(ca + ga);
+        const double2 x1 = *reinterpret_cast<const double2*>(ca + ga + 2);
+        const double2 y0 = *reinterpret_cast<const double2*>(cb + gb);
+        const double2 y1 = *reinterpret_cast<const double2*>(cb + gb + 2);
+        ra[h][0] = x0.x; ra[h][1] = x0.y; ra[h][2] = x1.x; ra[h][3] = x1.y;
+        rb[h][0] = y0.x; rb[h][1] = y0.y; rb[h][2] = y1.x; rb[h][3] = y1.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+          ra[h][e] = ca[rowa[e]];
+          rb[h][e] = cb[rowb[e]];
+        }
+      }
+    }
+  };
+  // masks are needed only in the last chunk when nelim is not a multiple of
+  // BK; the branch is uniform across the workgroup
+  auto store = [&](int buf, int kc) {
+    const bool full = (kc + 1) * BK <= K;
+#pragma unroll
+    for (int h = 0; h < KPT; ++h) {
+      const bool m = full || kv[h];
+      double2 a0, a1, b0, b1;
+      a0.x = m ? ra[h][0] : 0.0; a0.y = m ? ra[h][1] : 0.0;
+      a1.x = m ? ra[h][2] : 0.0; a1.y = m ? ra[h][3] : 0.0;
+      b0.x = m ? rb[h][0] : 0.0; b0.y = m ? rb[h][1] : 0.0;
+      b1.x = m ? rb[h][2] : 0.0; b1.y = m ? rb[h][3] : 0.0;
+      *reinterpret_cast<double2*>(&As[buf][kq + KSTEP * h][ii]) = a0;
+      *reinterpret_cast<double2*>(&As[buf][kq + KSTEP * h][ii + 2]) = a1;
+      *reinterpret_cast<double2*>(&Bs[buf][kq + KSTEP * h][ii]) = b0;
+      *reinterpret_cast<double2*>(&Bs[buf][kq + KSTEP * h][ii + 2]) = b1;
+    }
+  };
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+
+  if (nk > 0) {
+    load(0);
+    store(0, 0);
+    __syncthreads();
+  }
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) load(kc + 1);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double af[4], bf[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) af[x] = As[buf][ks + lk][wm * 64 + x * 16 + lrow];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) bf[y] = Bs[buf][ks + lk][wn * 64 + y * 16 + lrow];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    if (kc + 1 < nk) store(buf ^ 1, kc + 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wm * 64 + x * 16 + lk + 4 * q;
+        const int j = j0 + wn * 64 + y * 16 + lrow;
+        if (i < iend && j <= i) g.s[(size_t)j * g.lds + (i - g.row0)] = acc[x][y][q];
+      }
+}
+
+template <bool ALIGNED>
+__global__ __launch_bounds__(SC_THREADS, 2) void schur_w_kernel(SchurWArgs g) {
+  __shared__ double As[2][16][SC_BM];
+  __shared__ double Bs[2][16][SC_BN];
+  const int b = blockIdx.x;
+  const int tile = (b % SC_NXCD) * g.per_xcd + b / SC_NXCD;
+  if (tile >= g.ntm * g.ntn) return;
+  const int per_group = SC_GROUP * g.ntn;
+  const int grp = tile / per_group;
+  const int in_grp = tile % per_group;
+  const int gm = min(SC_GROUP, g.ntm - grp * SC_GROUP);
+  const int tm = grp * SC_GROUP + in_grp % gm;
+  const int tn = in_grp / gm;
+  const int i0 = g.row0 + tm * SC_BM;
+  const int j0 = tn * SC_BN;
+  const int iend = g.row0 + g.nrows;
+  if (j0 > min(i0 + SC_BM - 1, iend - 1)) return;   // strictly above the diagonal
+  const int K = min(max(*g.nelim_p, 0), g.p);
+  // j0 may exceed i0 when row0 is not a multiple of the tile: check both
+  if (ALIGNED && i0 + SC_BM <= g.r && j0 + SC_BN <= g.r) schur_w_tile<true>(g, i0, j0, K, As, Bs);
+  else schur_w_tile<false>(g, i0, j0, K, As, Bs);
+}
+
+int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int ldw,
+                   const int* nelim, int row0, int nrows, double* s, int lds, hipStream_t stream) {
+  SchurWArgs g;
+  g.r = n - p;
+  g.l21 = a + p;
+  g.lda = lda;
+  g.w = w;
+  g.ldw = ldw;
+  g.nelim_p = nelim;
+  g.p = p;
+  g.row0 = row0;
+  g.nrows = nrows;
+  g.s = s;
+  g.lds = lds;
+  g.ntm = (nrows + SC_BM - 1) / SC_BM;
+  g.ntn = (row0 + nrows + SC_BN - 1) / SC_BN;
+  const int total = g.ntm * g.ntn;
+  if (total == 0 || p == 0) return 0;
+  g.per_xcd = (total + SC_NXCD - 1) / SC_NXCD;
+  const unsigned grid = g.per_xcd * SC_NXCD;
+  // 16-byte loads need every column of both operands 16-byte aligned
+  const bool vec = ((reinterpret_cast<uintptr_t>(a + p + row0) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&
+                   lda % 2 == 0 && ldw % 2 == 0;
+  if (vec) schur_w_kernel<true><<<grid, SC_THREADS, 0, stream>>>(g);
+  else schur_w_kernel<false><<<grid, SC_THREADS, 0, stream>>>(g);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream) {

@@ -178,6 +178,46 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
   }
 }
 
+// W = L21 D for the eliminated columns, from L21 and D (used after the
+// threshold-partial-pivoting factorization, which leaves L21 in the panel
+// but no W).  One column per blockIdx.y; a 2x2 pivot mixes two columns.
+__global__ __launch_bounds__(256) void form_w_kernel(int r, int p, const double* __restrict__ l21,
+                                                     int lda, const int* __restrict__ piv,
+                                                     const double* __restrict__ d,
+                                                     const int* __restrict__ nelim_p,
+                                                     double* __restrict__ w, int ldw) {
+  const int k = blockIdx.y;
+  const int nelim = min(max(*nelim_p, 0), p);
+  if (k >= nelim) return;
+  const int pt = piv[k];
+  const int i0 = blockIdx.x * 4096;
+  const int i1 = min(r, i0 + 4096);
+  double* dst = w + (size_t)k * ldw;
+  const double* lk = l21 + (size_t)k * lda;
+  if (pt == PIV_2X2_FIRST || pt == PIV_2X2_SECOND) {
+    const int k1 = pt == PIV_2X2_FIRST ? k : k - 1;     // first column of the pair
+    const double* l1 = l21 + (size_t)k1 * lda;
+    const double* l2 = l1 + lda;
+    // column k of D restricted to the pair: (D(k1, k), D(k1+1, k))
+    const double c1 = pt == PIV_2X2_FIRST ? d[2 * k1] : d[2 * k1 + 1];
+    const double c2 = pt == PIV_2X2_FIRST ? d[2 * k1 + 1] : d[2 * k1 + 2];
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = l1[i] * c1 + l2[i] * c2;
+  } else {
+    const double dk = pt == PIV_1X1 ? d[2 * k] : 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = lk[i] * dk;
+  }
+}
+
+int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
+                  const int* nelim, double* w, int ldw, hipStream_t stream) {
+  const int r = n - p;
+  if (r <= 0 || p <= 0) return 0;
+  dim3 gg((r + 4095) / 4096, p);
+  form_w_kernel<<<gg, 256, 0, stream>>>(r, p, a + p, lda, piv, d, nelim, w, ldw);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
                  const double* d, const int* nelim, double* w, int ldw, hipStream_t stream) {
   const int r = n - p;

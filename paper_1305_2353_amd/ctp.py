@@ -60,7 +60,7 @@ def load(path=LIB_PATH):
         "ctp_factor_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
         "ctp_solve_supernode": (I, [I, I, P, I, P, P, P, P, OPT, P, SZ, P]),
         "ctp_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
-        "ctp_schur": (I, [I, I, P, I, P, P, P, I, I, P, I, OPT, P]),
+        "ctp_schur": (I, [I, I, P, I, P, P, P, I, I, P, I, OPT, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -182,13 +182,16 @@ def ctp_supernode(a, opts, work=None, outs=None):
     return {"perm": perm[:p], "piv": piv[:p], "d": d[:2 * p], "nelim": nelim, "status": status}
 
 
-def ctp_schur(a, f, row0, nrows, opts, s=None):
+def ctp_schur(a, f, row0, nrows, opts, s=None, work=None):
     """Rows row0..row0+nrows-1 of the lower triangle of S.  s: column-major
-    (nrows x (row0+nrows)) float64 CUDA tensor (allocated if None)."""
+    (nrows x (row0+nrows)) float64 CUDA tensor (allocated if None).  work:
+    the workspace filled by ctp_solve_supernode / ctp_supernode for this
+    panel (W = L21 D is read from it), or None to form W inside the kernel."""
     n, p, lda = _panel_args(a)
     if s is None:
         s = torch.zeros((row0 + nrows, max(nrows, 1)), dtype=torch.float64, device=a.device).t()[:nrows]
     lds = s.stride(1) if s.dim() == 2 and s.shape[1] > 1 else max(nrows, 1)
+    lwork = work.numel() if work is not None else 0
     _check(load().ctp_schur(n, p, _ptr(a), lda, _ptr(f["piv"]), _ptr(f["d"]), _ptr(f["nelim"]), row0, nrows,
-                            _ptr(s), lds, ctypes.byref(opts), _stream()), "ctp_schur")
+                            _ptr(s), lds, ctypes.byref(opts), _ptr(work), lwork, _stream()), "ctp_schur")
     return s

@@ -29,10 +29,14 @@ def run_supernode(A, p, method, u=0.01, small=1e-20, schur=True, lda=None):
     n = A.shape[0]
     a = ctp.device_panel(A, lda=lda)
     opts = ctp.ctp_default_opts(method, u=u, small=small)
-    f = ctp.ctp_supernode(a, opts)
-    s = None
+    work = ctp.workspace(n, p, opts)
+    f = ctp.ctp_supernode(a, opts, work=work)
+    s = s_direct = None
     if schur and n > p:
-        s = ctp.ctp_schur(a, f, 0, n - p, opts)
+        # from the W = L21 D that the solve left in the workspace ...
+        s = ctp.ctp_schur(a, f, 0, n - p, opts, work=work)
+        # ... and with W formed inside the Form kernel
+        s_direct = ctp.ctp_schur(a, f, 0, n - p, opts)
     torch.cuda.synchronize()
     res = {
         "out": a.cpu().numpy(),
@@ -44,6 +48,7 @@ def run_supernode(A, p, method, u=0.01, small=1e-20, schur=True, lda=None):
     }
     if s is not None:
         res["S"] = s.cpu().numpy()
+        res["S_direct"] = s_direct.cpu().numpy()
     return res
 
 
@@ -71,3 +76,4 @@ def assert_parity(g, ref, p, method, check_s=True):
     if check_s and n > p:
         S_ref = schur_rows(ref, np.arange(n - p))
         assert rel_err(np.tril(g["S"]), np.tril(S_ref)) <= FP64_TOL, method
+        assert rel_err(np.tril(g["S_direct"]), np.tril(S_ref)) <= FP64_TOL, method

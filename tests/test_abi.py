@@ -65,8 +65,9 @@ def test_workspace_size_and_argument_checks(lib):
                                     1 << 20, nul) == -4
     assert lib.ctp_factor_supernode(20, 10, fake, 20, ctypes.byref(o), fake, fake, fake, fake, fake, fake,
                                     0, nul) == -12
-    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 5, 6, fake, 6, ctypes.byref(o), nul) == -9
-    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 0, 6, fake, 5, ctypes.byref(o), nul) == -11
+    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 5, 6, fake, 6, ctypes.byref(o), None, 0, nul) == -9
+    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 0, 6, fake, 5, ctypes.byref(o), None, 0, nul) == -11
+    assert lib.ctp_schur(20, 10, fake, 20, fake, fake, fake, 0, 6, fake, 6, ctypes.byref(o), fake, 16, nul) == -14
     assert lib.ctp_solve_supernode(600, 513, fake, 600, fake, fake, fake, fake, ctypes.byref(o), fake,
                                    1 << 30, nul) == -2
     assert lib.ctp_solve_supernode(600, 50, fake, 600, fake, fake, fake, fake, ctypes.byref(o), fake,

@@ -54,15 +54,16 @@ def test_full_size_supernode(panel, method):
     assert rel_err(out[p:, :ref.nelim], ref.out[p:, :ref.nelim]) <= FP64_TOL
     assert rel_err(out[p:, ref.nelim:], ref.out[p:, ref.nelim:]) <= FP64_TOL
 
-    # S: three of the 25 row blocks, launched as the benchmark launches them,
-    # checked on sampled rows (first, last and random rows of the block).
+    # S: three of the 25 row blocks, launched as the benchmark launches them
+    # (from the W the solve left in the workspace), checked on sampled rows
+    # (first, last and random rows of the block).
     S = torch.empty((r, BLOCK), dtype=torch.float64, device=a.device).t()
     rng = np.random.default_rng(5)
     nblk = -(-r // BLOCK)
     for b in (0, nblk // 2, nblk - 1):
         row0 = b * BLOCK
         nr = min(BLOCK, r - row0)
-        ctp.ctp_schur(a, f, row0, nr, opts, s=S[:nr, :row0 + nr])
+        ctp.ctp_schur(a, f, row0, nr, opts, s=S[:nr, :row0 + nr], work=work)
         torch.cuda.synchronize()
         loc = np.unique(np.concatenate([[0, nr - 1], rng.integers(0, nr, 6)]))
         rows = row0 + loc
