@@ -90,7 +90,9 @@ typedef struct ctp_opts {
   double u;        /* threshold, 0 < u <= 0.5 (Section 2; default 0.01) */
   double small;    /* entries below small count as zero (default 1e-20) */
   int prec;        /* reserved: 0 = FP64 arithmetic everywhere */
-  int tile;        /* Form kernel staging variant: -1 or 0 = default, 1 = alternate */
+  int tile;        /* Form kernel schedule variant: -1 or 0 = default; with a stored W
+                      1 = no LDS padding, 2 = no padding + mid-chunk staging;
+                      with work = NULL 1 = two rows per staging thread */
   unsigned flags;  /* reserved, 0 */
 } ctp_opts;
 

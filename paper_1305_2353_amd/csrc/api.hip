@@ -18,7 +18,8 @@ int launch_schur(int n, int p, const double* a, int lda, const int* piv, const d
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream);
 int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int ldw,
-                   const int* nelim, int row0, int nrows, double* s, int lds, hipStream_t stream);
+                   const int* nelim, int row0, int nrows, double* s, int lds, int variant,
+                   hipStream_t stream);
 int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
                   const int* nelim, double* w, int ldw, hipStream_t stream);
 
@@ -204,7 +205,7 @@ int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const doub
     if (nrows == 0) return 0;
     const double* w =
         reinterpret_cast<const double*>(static_cast<const unsigned char*>(work) + ws.w_off);
-    return launch_schur_w(n, p, a, lda, w, ws.ldw, nelim, row0, nrows, s, lds, stream);
+    return launch_schur_w(n, p, a, lda, w, ws.ldw, nelim, row0, nrows, s, lds, opts->tile, stream);
   }
   if (nrows == 0) return 0;
   return launch_schur(n, p, a, lda, piv, d, nelim, row0, nrows, s, lds, opts->tile, stream);

@@ -215,14 +215,27 @@ struct SchurWArgs {
 // Main loop and epilogue of one tile.  VEC: every row of both operands
 // that this tile stages exists and each column is 16-byte aligned, so a
 // thread's 4 rows come in as two 16-byte loads; otherwise 4 clamped loads.
-template <bool VEC>
-__device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0, int K,
-                                             double (*As)[16][SC_BM], double (*Bs)[16][SC_BN]) {
+// VAR selects the schedule: bit 0 writes the next chunk into LDS after
+// three of the four k steps (so a chunk ends with the barrier alone), bit 1
+// pads the LDS rows by 8 doubles.  The default is both (VAR 3), the fastest
+// measured; a second register stage (loads two chunks ahead) spills.
+template <int VAR>
+struct SchurWShape {
+  static constexpr int LW = (VAR & 2) ? SC_BM + 8 : SC_BM;   // LDS row stride (doubles)
+  static constexpr int LDS_BYTES = 2 * 2 * 16 * LW * 8;       // two buffers, two operands
+};
+
+template <bool VEC, int VAR>
+__device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0, int K, double* lds) {
   constexpr int BK = 16;
   constexpr int RPT = 4;
   constexpr int TPK = SC_BM / RPT;          // 32 threads per k column
   constexpr int KSTEP = SC_THREADS / TPK;   // 8 k columns at once
   constexpr int KPT = BK / KSTEP;           // 2 k columns per thread
+  constexpr int LW = SchurWShape<VAR>::LW;
+  // As(buf, k, i) and Bs(buf, k, j)
+  double* const As = lds;
+  double* const Bs = lds + 2 * BK * LW;
   const int iend = g.row0 + g.nrows;
   const int nk = (K + BK - 1) / BK;
   const int tid = threadIdx.x;
@@ -239,13 +252,18 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
     rowb[e] = VEC ? gb + e : min(gb + e, g.r - 1);
   }
 
-  double ra[KPT][RPT], rb[KPT][RPT];
-  bool kv[KPT];
-  auto load = [&](int kc) {
+  struct Stage {
+    double ra[KPT][RPT], rb[KPT][RPT];
+    bool kv[KPT];
+  };
+  Stage st0;
+  auto load = [&](Stage& S, int kc) {
+    auto& ra = S.ra;
+    auto& rb = S.rb;
 #pragma unroll
     for (int h = 0; h < KPT; ++h) {
       const int k = kc * BK + kq + KSTEP * h;
-      kv[h] = k < K;
+      S.kv[h] = k < K;
       const int kk = min(k, K - 1);
       const double* ca = g.l21 + (size_t)kk * g.lda;
       const double* cb = g.w + (size_t)kk * g.ldw;
@@ -267,20 +285,24 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
   };
   // masks are needed only in the last chunk when nelim is not a multiple of
   // BK; the branch is uniform across the workgroup
-  auto store = [&](int buf, int kc) {
+  auto store = [&](Stage& S, int buf, int kc) {
+    const auto& ra = S.ra;
+    const auto& rb = S.rb;
     const bool full = (kc + 1) * BK <= K;
 #pragma unroll
     for (int h = 0; h < KPT; ++h) {
-      const bool m = full || kv[h];
+      const bool m = full || S.kv[h];
       double2 a0, a1, b0, b1;
       a0.x = m ? ra[h][0] : 0.0; a0.y = m ? ra[h][1] : 0.0;
       a1.x = m ? ra[h][2] : 0.0; a1.y = m ? ra[h][3] : 0.0;
       b0.x = m ? rb[h][0] : 0.0; b0.y = m ? rb[h][1] : 0.0;
       b1.x = m ? rb[h][2] : 0.0; b1.y = m ? rb[h][3] : 0.0;
-      *reinterpret_cast<double2*>(&As[buf][kq + KSTEP * h][ii]) = a0;
-      *reinterpret_cast<double2*>(&As[buf][kq + KSTEP * h][ii + 2]) = a1;
-      *reinterpret_cast<double2*>(&Bs[buf][kq + KSTEP * h][ii]) = b0;
-      *reinterpret_cast<double2*>(&Bs[buf][kq + KSTEP * h][ii + 2]) = b1;
+      double* pa = As + (buf * BK + kq + KSTEP * h) * LW + ii;
+      double* pb = Bs + (buf * BK + kq + KSTEP * h) * LW + ii;
+      *reinterpret_cast<double2*>(pa) = a0;
+      *reinterpret_cast<double2*>(pa + 2) = a1;
+      *reinterpret_cast<double2*>(pb) = b0;
+      *reinterpret_cast<double2*>(pb + 2) = b1;
     }
   };
 
@@ -290,31 +312,48 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
 
-  if (nk > 0) {
-    load(0);
-    store(0, 0);
-    __syncthreads();
-  }
   const int lrow = lane & 15;
   const int lk = lane >> 4;
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nk) load(kc + 1);
+  auto kstep = [&](int buf, int ks) {
+    double af[4], bf[4];
+    const double* pa = As + (buf * BK + ks + lk) * LW + wm * 64 + lrow;
+    const double* pb = Bs + (buf * BK + ks + lk) * LW + wn * 64 + lrow;
 #pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      double af[4], bf[4];
+    for (int x = 0; x < 4; ++x) af[x] = pa[x * 16];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) af[x] = As[buf][ks + lk][wm * 64 + x * 16 + lrow];
+    for (int y = 0; y < 4; ++y) bf[y] = pb[y * 16];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) bf[y] = Bs[buf][ks + lk][wn * 64 + y * 16 + lrow];
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y)
+        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+  };
+  // one chunk from LDS buffer buf; the next chunk (already in registers S)
+  // goes to the other buffer after three of the four k steps
+  auto chunk = [&](int buf, Stage& S, int kc) {
+    if (VAR & 1) {
+      kstep(buf, 0);
+      kstep(buf, 4);
+      kstep(buf, 8);
+      __builtin_amdgcn_sched_barrier(0);
+      if (kc + 1 < nk) store(S, buf ^ 1, kc + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      kstep(buf, 12);
+    } else {
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+      for (int ks = 0; ks < BK; ks += 4) kstep(buf, ks);
+      if (kc + 1 < nk) store(S, buf ^ 1, kc + 1);
     }
-    if (kc + 1 < nk) store(buf ^ 1, kc + 1);
     __syncthreads();
+  };
+  if (nk > 0) {
+    load(st0, 0);
+    store(st0, 0, 0);
+    __syncthreads();
+  }
+  for (int kc = 0; kc < nk; ++kc) {
+    if (kc + 1 < nk) load(st0, kc + 1);
+    chunk(kc & 1, st0, kc);
   }
 
 #pragma unroll
@@ -329,10 +368,10 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
       }
 }
 
-template <bool ALIGNED>
+extern __shared__ double sc_dyn[];
+
+template <bool ALIGNED, int VAR>
 __global__ __launch_bounds__(SC_THREADS, 2) void schur_w_kernel(SchurWArgs g) {
-  __shared__ double As[2][16][SC_BM];
-  __shared__ double Bs[2][16][SC_BN];
   const int b = blockIdx.x;
   const int tile = (b % SC_NXCD) * g.per_xcd + b / SC_NXCD;
   if (tile >= g.ntm * g.ntn) return;
@@ -348,12 +387,26 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_w_kernel(SchurWArgs g) {
   if (j0 > min(i0 + SC_BM - 1, iend - 1)) return;   // strictly above the diagonal
   const int K = min(max(*g.nelim_p, 0), g.p);
   // j0 may exceed i0 when row0 is not a multiple of the tile: check both
-  if (ALIGNED && i0 + SC_BM <= g.r && j0 + SC_BN <= g.r) schur_w_tile<true>(g, i0, j0, K, As, Bs);
-  else schur_w_tile<false>(g, i0, j0, K, As, Bs);
+  if (ALIGNED && i0 + SC_BM <= g.r && j0 + SC_BN <= g.r) schur_w_tile<true, VAR>(g, i0, j0, K, sc_dyn);
+  else schur_w_tile<false, VAR>(g, i0, j0, K, sc_dyn);
+}
+
+template <int VAR>
+static int launch_schur_w_var(const SchurWArgs& g, bool vec, unsigned grid, hipStream_t stream) {
+  constexpr int bytes = SchurWShape<VAR>::LDS_BYTES;
+  auto kern = vec ? schur_w_kernel<true, VAR> : schur_w_kernel<false, VAR>;
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  }
+  kern<<<grid, SC_THREADS, bytes, stream>>>(g);
+  return 0;
 }
 
 int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int ldw,
-                   const int* nelim, int row0, int nrows, double* s, int lds, hipStream_t stream) {
+                   const int* nelim, int row0, int nrows, double* s, int lds, int variant,
+                   hipStream_t stream) {
   SchurWArgs g;
   g.r = n - p;
   g.l21 = a + p;
@@ -375,8 +428,13 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
   // 16-byte loads need every column of both operands 16-byte aligned
   const bool vec = ((reinterpret_cast<uintptr_t>(a + p + row0) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&
                    lda % 2 == 0 && ldw % 2 == 0;
-  if (vec) schur_w_kernel<true><<<grid, SC_THREADS, 0, stream>>>(g);
-  else schur_w_kernel<false><<<grid, SC_THREADS, 0, stream>>>(g);
+  int rc;
+  switch (variant) {
+    case 1: rc = launch_schur_w_var<0>(g, vec, grid, stream); break;
+    case 2: rc = launch_schur_w_var<1>(g, vec, grid, stream); break;
+    default: rc = launch_schur_w_var<3>(g, vec, grid, stream); break;
+  }
+  if (rc) return rc;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
