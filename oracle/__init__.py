@@ -20,4 +20,4 @@ the interchanges for a 2x2 pivot are fixed only by this implementation; no
 value printed in the paper checks them beyond internal consistency.
 """
 
-from . import threshold, supernode  # noqa: F401
+from . import threshold, supernode, dense  # noqa: F401

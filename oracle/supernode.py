@@ -192,10 +192,12 @@ def solve_a21(A21P, L, piv, d, nelim):
     return L21, W, A21d
 
 
-def factor_supernode(A, p, method="relaxed", u=0.01, small=1e-20, forced=None):
+def factor_supernode(A, p, method="relaxed", u=0.01, small=1e-20, forced=None, root=False):
     """Factor + Solve of the n x p supernode A = [A11; A21] (Section 1).
 
     A: n x p array; the lower triangle of its first p rows is A11.
+    root: eliminate every column (last panel of a factorization; see
+    factor_trapezoid).
     """
     if method not in METHODS:
         raise ValueError(method)
@@ -204,15 +206,15 @@ def factor_supernode(A, p, method="relaxed", u=0.01, small=1e-20, forced=None):
     A21 = A[p:, :p]
     C = crow = None
     if method == "tpp":
-        trap = factor_trapezoid(A11, A21, u, small, R_NORMAL, forced)
+        trap = factor_trapezoid(A11, A21, u, small, R_NORMAL, forced, root)
     elif method == "strict":
         C = compress_strict(A21)
-        trap = factor_trapezoid(A11, C, u, small, R_ABS, forced)
+        trap = factor_trapezoid(A11, C, u, small, R_ABS, forced, root)
     elif method == "relaxed":
         C, crow = compress_relaxed(A21)
-        trap = factor_trapezoid(A11, C, u, small, R_NORMAL, forced)
+        trap = factor_trapezoid(A11, C, u, small, R_NORMAL, forced, root)
     else:
-        trap = factor_trapezoid(A11, A21[:0], u, small, R_NORMAL, forced)
+        trap = factor_trapezoid(A11, A21[:0], u, small, R_NORMAL, forced, root)
 
     perm, piv, d, nelim = trap.perm, trap.piv, trap.d, trap.nelim
     out = np.zeros_like(A)

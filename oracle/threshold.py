@@ -208,6 +208,19 @@ def accept_2x2(a_tt, a_tm, a_mm, maxt, maxm, u, small):
     return (g_t <= inv_u) and (g_m <= inv_u), margins
 
 
+def det_ok(a_tt, a_tm, a_mm, small):
+    """The non-singularity part of the 2x2 test alone (Section 2; reading
+    C2/C3): scaled determinant clear of cancellation and of small."""
+    big = max(abs(a_tt), abs(a_tm), abs(a_mm))
+    if big < small:
+        return False
+    s = 1 / big
+    det1 = (a_tm * s) * a_tm
+    det0 = (a_mm * s) * a_tt
+    det = det0 - det1
+    return abs(det) > max(small, abs(det0) / 2, abs(det1) / 2)
+
+
 def accept_1x1(a_mm, maxm, u):
     """1x1 acceptance test |a_mm| >= u * maxm (Section 2, eq. (2.1))."""
     bound = u * maxm
@@ -290,7 +303,7 @@ def _col_values(T, R, nelim, m, exclude):
     return np.concatenate([top, R[:, m]])
 
 
-def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None):
+def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None, root=False):
     """Threshold pivoting (Section 2, Listing 1) on the trapezoid [A11; R].
 
     A11: p x p, only its lower triangle is read.  R: r x p (may have r = 0).
@@ -298,6 +311,13 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
     ('1x1', col), ('2x2', col_t, col_m) or ('zero', col) with original
     column ids; the loop stops when the list is used up.  (Used to replay a
     pivot order stated in the paper.)
+    root: the last panel of a factorization, where every column must be
+    eliminated (Section 1 says all pivots are eliminated in the final
+    supernode; the paper gives no mechanism).  When a pass makes no progress
+    the column at position nelim is eliminated regardless of u: as a 1x1 if
+    |a(k,k)| >= small, else as a 2x2 with column k+1 if its determinant
+    passes the nonsingularity test, else as a zero pivot.  Then the normal
+    loop resumes with a new pass.  Each such step is logged as 'fallback'.
     """
     p = A11.shape[0]
     T = symmetric_from_lower(A11)
@@ -364,12 +384,29 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
                 raise ValueError(dec)
         return TrapezoidFactors(T, R, perm, piv, d, nelim, log)
 
+    def fallback_step():
+        k = nelim
+        if abs(T[k, k]) >= small:
+            log.append(Decision("fallback", (int(perm[k]),), (k,), nelim))
+            record_1x1(k)
+            return
+        if k + 1 < p and det_ok(T[k, k], T[k + 1, k], T[k + 1, k + 1], small):
+            log.append(Decision("fallback", (int(perm[k]), int(perm[k + 1])), (k, k + 1), nelim))
+            record_2x2(k, k + 1)
+            return
+        log.append(Decision("fallback", (int(perm[k]),), (k,), nelim))
+        record_zero(k)
+
     m = 1 if p >= 2 else 0
     progress = True
     while nelim < p:
         if m >= p:
             if not progress:
-                break
+                if not root:
+                    break
+                fallback_step()
+                m = nelim
+                continue
             progress = False
             m = nelim
             log.append(Decision("pass", (), (m,), nelim))
