@@ -92,6 +92,116 @@ def cpu_baseline(A, p, method, blocks):
                       f"4096-row blocks {list(blocks)} of {-(-r // BLOCK_ROWS)}"}
 
 
+def dense_section(N, pw=256, method="relaxed", seed=0, nrhs=8, tol=1e-14):
+    """Dense symmetric indefinite system of order N (Q diag(lam) Q^T, half of
+    lam negative, |lam| in [1e-3, 1]) factorized right-looking in panels of
+    pw columns with compressed pivoting, then solved for nrhs right-hand
+    sides with FP64 refinement to a backward error <= tol.  Run with the
+    trailing update in FP64, FP32 and BF16 (FP32 accumulation).  Times are
+    wall clock around each call on a resident matrix (the factorization
+    reads nelim back after every panel)."""
+    import torch
+    from paper_1305_2353_amd import ctp
+    from workloads import dense_indefinite_torch
+    A, lam, B = dense_indefinite_torch(N, seed=seed, lam_lo=1e-3, nrhs=nrhs)
+    a0 = A.t()                          # symmetric: column-major view of the same matrix
+    b = B.t().contiguous().t()          # column-major N x nrhs
+    torch.cuda.synchronize()
+    flops = N ** 3 / 3.0
+    res = {"workload": f"dense N={N} Q diag(lam) Q^T, |lam| in [1e-3,1], {nrhs} RHS, panels of {pw}, {method}",
+           "flop_factor": flops}
+    for prec, steps_max in (("fp64", 10), ("fp32", 10), ("bf16", 30)):
+        opts = ctp.ctp_default_opts(method, prec=prec)
+        work = ctp.dense_workspace(N, pw, opts, nrhs)
+        best = None
+        for rep in range(2):
+            a = a0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = ctp.ctp_ldlt_dense(a, pw, opts, work)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, steps, hist = ctp.ctp_ldlt_refine(a0, a, f, b, opts, work, tol=tol, max_steps=steps_max)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            cur = {"factor_ms": round((t1 - t0) * 1e3, 2), "refine_ms": round((t2 - t1) * 1e3, 2),
+                   "total_ms": round((t2 - t0) * 1e3, 2), "refine_steps": steps,
+                   "bwd_err": hist[-1], "bwd_hist": [float("%.3g" % h) for h in hist],
+                   "reached": bool(hist[-1] <= tol), "panels": f["npanels"],
+                   "status": int(f["status"].item())}
+            if best is None or cur["total_ms"] < best["total_ms"]:
+                best = cur
+        best["factor_gflops"] = round(flops / (best["factor_ms"] * 1e-3) / 1e9, 1)
+        res[prec] = best
+        del work
+    ok = [p for p in ("fp32", "bf16") if res[p]["reached"]]
+    fastest = min(ok, key=lambda p: res[p]["total_ms"]) if ok else None
+    res["fastest_mixed"] = fastest
+    res["mixed_beats_fp64"] = bool(fastest and res["fp64"]["reached"]
+                                   and res[fastest]["total_ms"] < res["fp64"]["total_ms"])
+    return res
+
+
+def batch_section(count=4096, seed=0, method="relaxed", reps=3):
+    """One multifrontal level: `count` independent supernodes, n log-uniform
+    in [64, 8192], p uniform in [8, min(256, n/4)], 1% of each A11 diagonal
+    scaled by 1e-8.  Factor + Solve + Form of every node in one fixed
+    launch sequence (persistent work-queue Form, S of every node kept in
+    HBM as lower 128 x 128 tiles), Form schedule chosen by the autotuner,
+    the whole batch (with the restore of the pristine panels) captured in a
+    HIP graph and replayed; times are graph replays."""
+    import numpy as np
+    import torch
+    from paper_1305_2353_amd import autotune, ctp
+    from workloads import batch_panel_torch, batch_shapes
+    ns, ps = batch_shapes(count, seed=seed)
+    opts = ctp.ctp_default_opts(method)
+    b = ctp.Batch(list(zip(ns, ps)), opts, form=True, tiled=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    for i, (n, p) in enumerate(zip(ns, ps)):
+        b.panel_view(i).copy_(batch_panel_torch(int(n), int(p), gen))
+    pristine = b.panels.clone()
+    torch.cuda.synchronize()
+    tune = autotune.tune_batch(b, pristine)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            b.panels.copy_(pristine)
+            b.run()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    # the restore copy is part of the replay; time it alone to report the batch itself
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.panels.copy_(pristine)
+    e1.record()
+    e1.synchronize()
+    copy_ms = e0.elapsed_time(e1)
+    nelim = b.nelim[:count].cpu().numpy().astype(float)
+    r = (ns - ps).astype(float)
+    flops = float((ps ** 3 / 3.0 + r * nelim ** 2 + 2 * r * nelim * (ps - nelim) + r * (r + 1) * nelim).sum())
+    ms = float(np.median(times))
+    return {"workload": f"{count} supernodes, n log-uniform [64, 8192], p uniform [8, min(256, n/4)], "
+                        f"1% of diag x 1e-8, {method}",
+            "replay_ms": round(ms, 3), "panel_restore_ms": round(copy_ms, 3),
+            "batch_ms": round(ms - copy_ms, 3), "algorithmic_gflop": round(flops / 1e9, 1),
+            "gflops": round(flops / ((ms - copy_ms) * 1e-3) / 1e9, 1), "tiles": int(b.info.tiles),
+            "s_gbytes": round(b.S.numel() * 8 / 1e9, 1), "delayed_total": int((ps - nelim).sum()),
+            "status_nonzero": int((b.status[:count].cpu().numpy() != 0).sum()),
+            "autotune": tune["best"], "graph": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +213,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tpp", action="store_true")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense mixed-precision section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-supernode section")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--dense-n", type=int, default=16384)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -233,6 +347,14 @@ def main():
         result["tpp"] = {"factor_solve_ms": round(tpp_ms, 3), "nelim": int(tf["nelim"].item()),
                          "compressed_factor_solve_ms": round(cmp_ms, 3),
                          "speedup_compressed_vs_tpp": round(tpp_ms / cmp_ms, 2) if cmp_ms > 0 else None}
+
+    if not args.no_dense:
+        result["dense"] = dense_section(args.dense_n)
+
+    if not args.no_batch:
+        del S, pristine, a, work
+        torch.cuda.empty_cache()
+        result["batch"] = batch_section(args.batch_count)
 
     if not args.no_cpu_baseline:
         nb = len(blocks)

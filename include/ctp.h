@@ -79,8 +79,24 @@ extern "C" {
 #define CTP_STATUS_ZERO_PIVOT 1     /* a zero pivot was recorded */
 #define CTP_STATUS_NONFINITE 2      /* a NaN/Inf reached a pivot test */
 #define CTP_STATUS_RELAXED_RESCAN 4 /* relaxed C needed a full column rescan */
+#define CTP_STATUS_ROOT_FALLBACK 8  /* CTP_FLAG_ROOT: a column was eliminated regardless of u */
+
+/* ctp_opts.flags bits. */
+#define CTP_FLAG_ROOT 1u   /* last panel of a factorization: eliminate every column
+                              (a pass without progress eliminates the column at
+                              position nelim regardless of u: 1x1 unless below
+                              small, else a 2x2 with the next column if its
+                              determinant is safely nonzero, else a zero pivot) */
+#define CTP_FLAG_S_TILED 4u /* batches: each node's S is stored as the 128 x 128 tiles of
+                              its lower triangle, tile t = tm (tm + 1) / 2 + tn (tn <= tm)
+                              at s + s_off + t * 16384, each column-major with ld 128
+                              (rows past n - p of edge tiles are not written) */
+#define CTP_FLAG_ONE_WG 2u /* run the whole pivot search in one workgroup (decide
+                              and apply in the same kernel, no per-batch
+                              launches); same results, bit for bit */
 
 #define CTP_ERR_HIP_BASE (-1000)
+#define CTP_ERR_PANEL_TOO_WIDE (-900)  /* dense: delays grew a panel past CTP_MAX_P */
 
 /* Largest p supported by the single-workgroup pivot search and the solve. */
 #define CTP_MAX_P 512
@@ -89,11 +105,14 @@ typedef struct ctp_opts {
   int method;      /* CTP_TPP, CTP_STRICT, CTP_RELAXED or CTP_RESTRICTED */
   double u;        /* threshold, 0 < u <= 0.5 (Section 2; default 0.01) */
   double small;    /* entries below small count as zero (default 1e-20) */
-  int prec;        /* reserved: 0 = FP64 arithmetic everywhere */
+  int prec;        /* dense factorization only: trailing update in 0 = FP64,
+                      1 = FP32 matrix cores, 2 = BF16 matrix cores (FP32
+                      accumulation, FP32 trailing matrix); the supernode
+                      entry points always compute in FP64 */
   int tile;        /* Form kernel schedule variant: -1 or 0 = default; with a stored W
                       1 = no LDS padding, 2 = no padding + mid-chunk staging;
                       with work = NULL 1 = two rows per staging thread */
-  unsigned flags;  /* reserved, 0 */
+  unsigned flags;  /* CTP_FLAG_* bits, default 0 */
 } ctp_opts;
 
 /* Fill *opts with the defaults: relaxed, u = 0.01, small = 1e-20. */
@@ -179,6 +198,121 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
               const int* nelim, int row0, int nrows, double* s, int lds,
               const ctp_opts* opts, const void* work, size_t lwork, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent supernodes (one level of a multifrontal tree,
+ * Section 1): Factor + Solve (+ Form) of every node in a fixed sequence of
+ * launches over the whole batch, with no host synchronization, so the call
+ * can be captured in a HIP graph.  Compressed and restricted rules only
+ * (opts->method CTP_STRICT / CTP_RELAXED / CTP_RESTRICTED).
+ *   1. compression of every A21 (one grid over all nodes);
+ *   2. the pivot search of each node in one workgroup (CTP_FLAG_ONE_WG);
+ *   3. Solve of every node;
+ *   4. Form: one persistent launch whose workgroups take 128 x 128 tiles of
+ *      all the nodes' S from a shared counter (opts->tile picks the tile
+ *      schedule, as for ctp_schur).
+ * ------------------------------------------------------------------------ */
+
+typedef struct ctp_node {
+  int n, p;            /* shape: 1 <= p <= CTP_MAX_P, n >= p */
+  int lda;             /* panel leading dimension, >= n */
+  int lds;             /* S leading dimension, >= n - p (ignored without S or with
+                          CTP_FLAG_S_TILED) */
+  long long a_off;     /* panel: panels + a_off (doubles), column-major n x p */
+  long long s_off;     /* S: s + s_off (doubles), (n-p) x (n-p) lower; -1: no Form */
+  long long out_off;   /* perm / piv + out_off (p ints), d + 2*out_off (2p doubles) */
+  long long work_off;  /* set by ctp_batch_plan: the node's workspace (bytes) */
+  long long tile_off;  /* set by ctp_batch_plan: its first Form tile */
+} ctp_node;
+
+typedef struct ctp_batch_info {
+  size_t work_bytes;   /* workspace bytes for the batch */
+  long long tiles;     /* Form tiles over all nodes with S */
+  int count, max_p, max_r, max_chunks;
+  int form_workgroups; /* persistent Form workgroups (0: default 512) */
+} ctp_batch_info;
+
+/* Host-side plan: checks every node of nodes[count] (host memory), fills
+ * work_off and tile_off, and the totals in *info.  The caller then copies
+ * the nodes array to the device for ctp_supernode_batched. */
+int ctp_batch_plan(int count, ctp_node* nodes, const ctp_opts* opts, ctp_batch_info* info);
+
+/* Factor + Solve (+ Form where s_off >= 0 and s != NULL) of every node.
+ * nodes: device copy of the planned array; panels: every node's panel (in
+ * place, as ctp_supernode); s: the S buffer (may be NULL); perm, piv, d:
+ * outputs at each node's out_off; nelim[count], status[count]: device
+ * outputs per node.  work: info->work_bytes bytes.  No host
+ * synchronization, no allocation. */
+int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                          double* s, int* perm, int* piv, double* d, int* nelim, int* status,
+                          const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Dense symmetric indefinite LDL^T from supernode panels (Section 1: the
+ * Factor / Solve / Form tasks chained right-looking, failed pivots delayed
+ * to the next panel, the last panel eliminating every column).
+ *
+ * Panel = the delayed columns of the previous panel followed by the next pw
+ * columns, with every row below them; each is one ctp_supernode call with
+ * the rule in opts->method (the last with CTP_FLAG_ROOT), and the trailing
+ * matrix receives the Form product, subtracted.  With opts->prec = 1 / 2
+ * the trailing matrix is kept in FP32 and updated on the FP32 / BF16 matrix
+ * cores; the panels are still factorized in FP64.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for ctp_ldlt_dense / ctp_ldlt_solve / ctp_ldlt_refine
+ * with order N, panel width pw (1..CTP_MAX_P), opts->method / prec, and up
+ * to nrhs_max right-hand sides (0..16) per solve. */
+int ctp_dense_workspace_size(int N, int pw, const ctp_opts* opts, int nrhs_max, size_t* bytes);
+
+/* P A P^T = L D L^T.  a: N x N column-major, lda >= N, device; on entry its
+ * lower triangle holds A (the upper triangle is not read).  On exit the
+ * lower triangle holds L below the diagonal and D on the diagonal and on
+ * the sub-diagonal of each 2x2 block (as for a supernode), and the strict
+ * upper triangle holds L^T (with zeros for the 2x2 sub-diagonals), which
+ * the solve reads.  perm[N]: A row / column at position i is perm[i];
+ * piv[N], d[2N]: pivot types and D as for a supernode.  status: device
+ * int, OR of the panels' CTP_STATUS_* bits.  npanels: host int (may be
+ * NULL), number of panels.  work: ctp_dense_workspace_size bytes; it also
+ * keeps the inverses of L's diagonal blocks for ctp_ldlt_solve, so pass the
+ * same workspace, unchanged, to the solve.  The call synchronizes the
+ * stream once per panel (panel widths depend on the delays).  Errors:
+ * -1..-12 argument k, CTP_ERR_PANEL_TOO_WIDE when delays pile up past
+ * CTP_MAX_P, supernode errors passed through. */
+int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                   double* d, int* status, int* npanels, void* work, size_t lwork,
+                   hipStream_t stream);
+
+/* b <- A^-1 b for nrhs (<= 16) columns, with the factors of ctp_ldlt_dense
+ * (a, perm, piv, d and the same workspace; opts and pw as for the
+ * factorization).  FP64. */
+int ctp_ldlt_solve(int N, int nrhs, const double* a, int lda, const int* perm, const int* piv,
+                   const double* d, double* b, int ldb, const ctp_opts* opts, int pw, void* work,
+                   size_t lwork, hipStream_t stream);
+
+/* Iterative refinement in FP64 (Section 7 measures accuracy by the
+ * backward error): x = solve(b), then x += solve(b - A0 x) until
+ *     max_c ||b - A0 x||_inf / (||A0||_inf ||x||_inf + ||b||_inf) <= tol
+ * or max_steps corrections.  a0: the original matrix with BOTH triangles
+ * (lda0), f / ldf: the factor array of ctp_ldlt_dense; x (N x nrhs, ldx)
+ * output.  steps (host, may be NULL): corrections applied; bwd_hist (host,
+ * may be NULL, max_steps + 1 entries): backward error before each
+ * correction and after the last.  Synchronizes once per step. */
+int ctp_ldlt_refine(int N, int nrhs, const double* a0, int lda0, const double* f, int ldf,
+                    const int* perm, const int* piv, const double* d, const double* b, int ldb,
+                    double* x, int ldx, const ctp_opts* opts, int pw, double tol, int max_steps,
+                    int* steps, double* bwd_hist, void* work, size_t lwork, hipStream_t stream);
+
+/* Adjoint of x = A^-1 b with the stored factors, pivots frozen (the
+ * derivative of the solve; not in the paper).  For symmetric A:
+ *     bbar = A^-1 xbar,   Abar = -(1/2) sum_c (bbar_c x_c^T + x_c bbar_c^T).
+ * xbar (N x nrhs, ldxb) is overwritten by bbar; abar (N x N, ldg) receives
+ * the full symmetric Abar.  a, perm, piv, d, opts, pw, work as for
+ * ctp_ldlt_solve; x: the forward solution. */
+int ctp_ldlt_adjoint(int N, int nrhs, const double* a, int lda, const int* perm, const int* piv,
+                     const double* d, const double* x, int ldx, double* xbar, int ldxb, double* abar,
+                     int ldg, const ctp_opts* opts, int pw, void* work, size_t lwork,
+                     hipStream_t stream);
 
 #ifdef __cplusplus
 }

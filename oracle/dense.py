@@ -53,6 +53,7 @@ class DenseFactors:
     d: np.ndarray        # 2N entries of D
     panels: list = field(default_factory=list)   # (k0, width, nelim) per panel
     fallback: int = 0    # number of root fallback eliminations
+    fragile: int = 0     # decisions within rounding of their threshold (all panels)
 
     @property
     def N(self):
@@ -76,6 +77,7 @@ def ldlt_dense(A, pw, method="relaxed", u=0.01, small=1e-20):
     d = np.zeros(2 * N)
     panels = []
     fallback = 0
+    fragile = 0
     k0 = 0
     width = min(pw, N)
     while k0 < N:
@@ -88,6 +90,7 @@ def ldlt_dense(A, pw, method="relaxed", u=0.01, small=1e-20):
         F = factor_supernode(panel, width, method, u, small, root=root)
         ne = F.nelim
         fallback += sum(1 for dec in F.log if dec.kind == "fallback")
+        fragile += len(F.trap.fragile_steps())
         panels.append((k0, width, ne))
         # symmetric interchanges inside the panel: earlier L rows and the
         # global permutation follow
@@ -107,7 +110,7 @@ def ldlt_dense(A, pw, method="relaxed", u=0.01, small=1e-20):
         if ne == 0 and not root:
             # nothing eliminated: the next panel grows by pw columns
             continue
-    return DenseFactors(M, perm, piv, d, panels, fallback)
+    return DenseFactors(M, perm, piv, d, panels, fallback, fragile)
 
 
 def reconstruct(F):
@@ -172,3 +175,15 @@ def refine(A, B, solve, tol=1e-14, max_steps=10):
         steps += 1
         hist.append(backward_error(A, X, B))
     return X, steps, hist
+
+
+def solve_adjoint(A, X, Xbar):
+    """Adjoint of X = A^-1 B for symmetric A with the pivots frozen (not in
+    the paper): Bbar = A^-1 Xbar and Abar = -sum_c (bbar_c x_c^T +
+    x_c bbar_c^T) / 2, the gradient for symmetric perturbations of A."""
+    A = np.asarray(A, dtype=float)
+    X = np.asarray(X, dtype=float).reshape(A.shape[0], -1)
+    Xbar = np.asarray(Xbar, dtype=float).reshape(A.shape[0], -1)
+    Bbar = np.linalg.solve(A, Xbar)
+    Abar = -0.5 * (Bbar @ X.T + X @ Bbar.T)
+    return Bbar, Abar

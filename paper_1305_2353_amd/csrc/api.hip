@@ -10,8 +10,8 @@ namespace ctp {
 int launch_compress(int n, int p, const double* a, int lda, int method, double* c, int ldc,
                     int* crow, int* status, void* work, hipStream_t stream);
 int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, int abs_update,
-                        double u, double small, int* perm, int* piv, double* d, int* nelim,
-                        int* status, void* state, double* wbuf, hipStream_t stream);
+                        int root, int one_wg, double u, double small, int* perm, int* piv, double* d,
+                        int* nelim, int* status, void* state, double* wbuf, hipStream_t stream);
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
                  const double* d, const int* nelim, double* w, int ldw, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
@@ -23,42 +23,19 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
 int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
                   const int* nelim, double* w, int ldw, hipStream_t stream);
 
-__global__ void clear_status_kernel(int* status) { *status = 0; }
+size_t batch_header_bytes(int count);
+int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags, double u, double small,
+                       double* panels, double* s, int* perm, int* piv, double* d, int* nelim, int* status,
+                       void* work, BatchNode** nodes_out, void** pargs_out, unsigned int** counter_out,
+                       hipStream_t stream);
+int launch_compress_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int max_chunks,
+                          hipStream_t stream);
+int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipStream_t stream);
+int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream);
+int launch_schur_batch(int count, const BatchNode* nodes, int method, long long total, int tiled,
+                       unsigned int* counter, int variant, int workgroups, hipStream_t stream);
 
-Workspace workspace_layout(int n, int p, int method) {
-  Workspace w;
-  const int r = n > p ? n - p : 0;
-  size_t off = 0;
-  if (method == CTP_STRICT || method == CTP_RELAXED) {
-    w.c_off = off;
-    off = align_up(off + (size_t)p * p * sizeof(double), 256);
-  }
-  if (method == CTP_STRICT) {
-    w.j_off = off;
-    off = align_up(off + (size_t)r * sizeof(int), 256);
-  }
-  if (method == CTP_RELAXED) {
-    w.relaxed_chunks = relaxed_chunk_count(r);
-    w.cand_off = off;
-    // Cand = {double, int} padded to 16 bytes
-    off = align_up(off + (size_t)p * w.relaxed_chunks * RELAXED_TOPK * 16, 256);
-    w.crow_off = off;
-    off = align_up(off + (size_t)p * sizeof(int), 256);
-  }
-  w.st_off = off;
-  off = align_up(off + (size_t)pivot_state_bytes(), 256);
-  w.wb_off = off;
-  off = align_up(off + pivot_wbuf_bytes(p), 256);
-  if (r > 0) {
-    w.ldw = (int)align_up((size_t)r, 32);
-    w.w_off = off;
-    off = align_up(off + (size_t)w.ldw * p * sizeof(double), 256);
-  }
-  w.misc_off = off;
-  off = align_up(off + 64 * sizeof(int), 256);
-  w.total = off;
-  return w;
-}
+__global__ void clear_status_kernel(int* status) { *status = 0; }
 
 static bool valid_method(int m) { return m >= CTP_TPP && m <= CTP_RESTRICTED; }
 
@@ -153,8 +130,10 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
     ldr = lda;
     rrows = r;
   }
-  return launch_pivot_factor(p, a, lda, rrows, R, ldr, abs_update, opts->u, opts->small, perm, piv,
-                             d, nelim, status, base + ws.st_off,
+  const int root = (opts->flags & CTP_FLAG_ROOT) ? 1 : 0;
+  const int one_wg = (opts->flags & CTP_FLAG_ONE_WG) ? 1 : 0;
+  return launch_pivot_factor(p, a, lda, rrows, R, ldr, abs_update, root, one_wg, opts->u, opts->small, perm,
+                             piv, d, nelim, status, base + ws.st_off,
                              reinterpret_cast<double*>(base + ws.wb_off), stream);
 }
 
@@ -209,6 +188,72 @@ int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const doub
   }
   if (nrows == 0) return 0;
   return launch_schur(n, p, a, lda, piv, d, nelim, row0, nrows, s, lds, opts->tile, stream);
+}
+
+
+
+int ctp_batch_plan(int count, ctp_node* nodes, const ctp_opts* opts, ctp_batch_info* info) {
+  if (count < 0) return -1;
+  if (count > 0 && !nodes) return -2;
+  if (check_opts(opts) || opts->method == CTP_TPP) return -3;
+  if (!info) return -4;
+  ctp_batch_info b;
+  std::memset(&b, 0, sizeof(b));
+  b.count = count;
+  size_t off = batch_header_bytes(count > 0 ? count : 1);
+  long long tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    ctp_node& nd = nodes[i];
+    if (nd.p < 1 || nd.p > CTP_MAX_P || nd.n < nd.p || nd.lda < nd.n || nd.a_off < 0 || nd.out_off < 0)
+      return -2;
+    const int r = nd.n - nd.p;
+    if (nd.s_off >= 0 && !(opts->flags & CTP_FLAG_S_TILED) && nd.lds < (r > 1 ? r : 1)) return -2;
+    Workspace ws = workspace_layout(nd.n, nd.p, opts->method);
+    nd.work_off = (long long)off;
+    off = align_up(off + ws.total, 256);
+    nd.tile_off = tiles;
+    if (nd.s_off >= 0) {
+      const long long nt = (r + 127) / 128;
+      tiles += nt * (nt + 1) / 2;
+    }
+    if (nd.p > b.max_p) b.max_p = nd.p;
+    if (r > b.max_r) b.max_r = r;
+    const int ch = relaxed_chunk_count(r);
+    if (ch > b.max_chunks) b.max_chunks = ch;
+  }
+  b.work_bytes = off;
+  b.tiles = tiles;
+  *info = b;
+  return 0;
+}
+
+int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                          double* s, int* perm, int* piv, double* d, int* nelim, int* status,
+                          const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream) {
+  if (count < 0) return -1;
+  if (count > 0 && !nodes) return -2;
+  if (!info || info->count != count) return -3;
+  if (count > 0 && (!panels || !perm || !piv || !d || !nelim || !status)) return -4;
+  if (check_opts(opts) || opts->method == CTP_TPP) return -11;
+  if (!work || lwork < info->work_bytes) return -12;
+  if (count == 0) return 0;
+  BatchNode* bn = nullptr;
+  void* pargs = nullptr;
+  unsigned int* counter = nullptr;
+  int rc = launch_batch_setup(count, nodes, opts->method, opts->flags, opts->u, opts->small, panels, s, perm, piv,
+                              d, nelim, status, work, &bn, &pargs, &counter, stream);
+  if (rc) return rc;
+  rc = launch_compress_batch(count, bn, opts->method, info->max_p, info->max_r, info->max_chunks, stream);
+  if (rc) return rc;
+  const int rrows = opts->method == CTP_RESTRICTED ? 0 : info->max_p;
+  rc = launch_pivot_batch(count, pargs, info->max_p, rrows, stream);
+  if (rc) return rc;
+  rc = launch_solve_batch(count, bn, opts->method, info->max_p, info->max_r, stream);
+  if (rc) return rc;
+  if (s && info->tiles > 0)
+    rc = launch_schur_batch(count, bn, opts->method, info->tiles, (opts->flags & CTP_FLAG_S_TILED) ? 1 : 0, counter,
+                            opts->tile, info->form_workgroups, stream);
+  return rc;
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@ constexpr int PIV_DELAYED = -1;
 constexpr int ST_ZERO_PIVOT = CTP_STATUS_ZERO_PIVOT;
 constexpr int ST_NONFINITE = CTP_STATUS_NONFINITE;
 constexpr int ST_RELAXED_RESCAN = CTP_STATUS_RELAXED_RESCAN;
+constexpr int ST_ROOT_FALLBACK = CTP_STATUS_ROOT_FALLBACK;
 
 // Number of top candidates kept per column by the relaxed compression.
 constexpr int RELAXED_TOPK = 8;
@@ -39,7 +40,11 @@ CTP_DEV double wave_max(double v) {
   return v;
 }
 
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block of the relaxed compression
+constexpr int PIV_NSLOT = 8;          // pending eliminated columns per batch of the pivot search
+constexpr int PIV_STATE_BYTES = 256;  // pivot-search state carried between launches
 
 // Workspace carve-up, shared by the size query and the launchers.
 struct Workspace {
@@ -56,9 +61,67 @@ struct Workspace {
   int relaxed_chunks = 0;
 };
 
-int relaxed_chunk_count(int rows);
-int pivot_state_bytes();
-size_t pivot_wbuf_bytes(int p);
-Workspace workspace_layout(int n, int p, int method);
+// One supernode of a batch as the kernels see it (built on the device from
+// the caller's ctp_node array and the base pointers).
+struct BatchNode {
+  int n, p, lda, lds;
+  int nchunks;            // relaxed compression chunks of its A21
+  int ntiles;             // Form tiles of its S
+  long long tile_off;     // first Form tile in the batch numbering
+  double* a;              // panel
+  double* s;              // S, or null
+  int* perm;
+  int* piv;
+  double* d;
+  int* nelim;
+  int* status;
+  unsigned char* work;    // this node's workspace (workspace_layout(n, p, method))
+};
+
+__host__ __device__ inline int relaxed_chunk_count(int rows) {
+  return rows <= 0 ? 1 : (rows + RELAXED_CHUNK - 1) / RELAXED_CHUNK;
+}
+__host__ __device__ inline int pivot_state_bytes() { return PIV_STATE_BYTES; }
+__host__ __device__ inline size_t pivot_wbuf_bytes(int p) {
+  return align_up((size_t)PIV_NSLOT * (p > 0 ? p : 1) * sizeof(double), 256);
+}
+
+// Workspace carve-up of one supernode (host: size query and launchers;
+// device: the batched kernels find each node's buffers).
+__host__ __device__ inline Workspace workspace_layout(int n, int p, int method) {
+  Workspace w;
+  const int r = n > p ? n - p : 0;
+  size_t off = 0;
+  if (method == CTP_STRICT || method == CTP_RELAXED) {
+    w.c_off = off;
+    off = align_up(off + (size_t)p * p * sizeof(double), 256);
+  }
+  if (method == CTP_STRICT) {
+    w.j_off = off;
+    off = align_up(off + (size_t)r * sizeof(int), 256);
+  }
+  if (method == CTP_RELAXED) {
+    w.relaxed_chunks = relaxed_chunk_count(r);
+    w.cand_off = off;
+    // Cand = {double, int} padded to 16 bytes
+    off = align_up(off + (size_t)p * w.relaxed_chunks * RELAXED_TOPK * 16, 256);
+    w.crow_off = off;
+    off = align_up(off + (size_t)p * sizeof(int), 256);
+  }
+  w.st_off = off;
+  off = align_up(off + (size_t)pivot_state_bytes(), 256);
+  w.wb_off = off;
+  off = align_up(off + pivot_wbuf_bytes(p), 256);
+  if (r > 0) {
+    w.ldw = (int)align_up((size_t)r, 32);
+    w.w_off = off;
+    off = align_up(off + (size_t)w.ldw * p * sizeof(double), 256);
+  }
+  w.misc_off = off;
+  off = align_up(off + 64 * sizeof(int), 256);
+  w.total = off;
+  return w;
+}
+
 
 }  // namespace ctp

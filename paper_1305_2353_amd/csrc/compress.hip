@@ -28,9 +28,7 @@ namespace ctp {
 
 constexpr int STRICT_CG = 8;          // columns per workgroup in pass 2
 constexpr int STRICT_ROWS = 4096;     // rows per workgroup in pass 2
-constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block
 
-int relaxed_chunk_count(int rows) { return rows <= 0 ? 1 : (rows + RELAXED_CHUNK - 1) / RELAXED_CHUNK; }
 
 __global__ void fill_u64_kernel(unsigned long long* x, size_t count, unsigned long long v) {
   size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,10 +41,8 @@ __global__ void fill_i32_kernel(int* x, int count, int v) {
   if (i < count) x[i] = v;
 }
 
-__global__ __launch_bounds__(256) void strict_rowset_kernel(int r, int p, const double* __restrict__ a21,
-                                                          int lda, int* __restrict__ J,
-                                                          int* __restrict__ status) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+CTP_DEV void strict_rowset_body(int r, int p, const double* __restrict__ a21, int lda, int* __restrict__ J,
+                                int* __restrict__ status, int i) {
   if (i >= r) return;
   const double* row = a21 + i;
   double best = -1.0;
@@ -73,14 +69,22 @@ __global__ __launch_bounds__(256) void strict_rowset_kernel(int r, int p, const 
   if (!finite) atomicOr(status, ST_NONFINITE);
 }
 
+__global__ __launch_bounds__(256) void strict_rowset_kernel(int r, int p, const double* __restrict__ a21,
+                                                          int lda, int* __restrict__ J,
+                                                          int* __restrict__ status) {
+  strict_rowset_body(r, p, a21, lda, J, status, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // Dynamic LDS: p * STRICT_CG u64 bins.
-__global__ __launch_bounds__(256) void strict_colmax_kernel(int r, int p, const double* __restrict__ a21,
-                                                          int lda, const int* __restrict__ J,
-                                                          unsigned long long* __restrict__ cbits, int ldc) {
-  extern __shared__ unsigned long long bins[];
-  const int k0 = blockIdx.y * STRICT_CG;
+extern __shared__ unsigned long long cmp_bins[];
+
+CTP_DEV void strict_colmax_body(int r, int p, const double* __restrict__ a21, int lda,
+                                const int* __restrict__ J, unsigned long long* __restrict__ cbits, int ldc,
+                                int bx, int by) {
+  unsigned long long* bins = cmp_bins;
+  const int k0 = by * STRICT_CG;
   const int ncol = min(STRICT_CG, p - k0);
-  const int i0 = blockIdx.x * STRICT_ROWS;
+  const int i0 = bx * STRICT_ROWS;
   const int i1 = min(r, i0 + STRICT_ROWS);
   for (int q = threadIdx.x; q < p * STRICT_CG; q += blockDim.x) bins[q] = 0ull;
   __syncthreads();
@@ -103,6 +107,12 @@ __global__ __launch_bounds__(256) void strict_colmax_kernel(int r, int p, const 
   }
 }
 
+__global__ __launch_bounds__(256) void strict_colmax_kernel(int r, int p, const double* __restrict__ a21,
+                                                          int lda, const int* __restrict__ J,
+                                                          unsigned long long* __restrict__ cbits, int ldc) {
+  strict_colmax_body(r, p, a21, lda, J, cbits, ldc, blockIdx.x, blockIdx.y);
+}
+
 // ---------------------------------------------------------------------------
 // Relaxed compression
 // ---------------------------------------------------------------------------
@@ -118,12 +128,9 @@ CTP_DEV bool better(double v1, int i1, double v2, int i2) {
 
 // Grid (column, chunk).  Writes RELAXED_TOPK candidates per (column, chunk)
 // to cand[(col * nchunks + chunk) * K + q], best first; missing -> v = -1.
-__global__ __launch_bounds__(256) void relaxed_topk_kernel(int r, int p, const double* __restrict__ a21,
-                                                         int lda, int nchunks, Cand* __restrict__ cand,
-                                                         int* __restrict__ status) {
+CTP_DEV void relaxed_topk_body(int r, int p, const double* __restrict__ a21, int lda, int nchunks,
+                               Cand* __restrict__ cand, int* __restrict__ status, int col, int chunk) {
   constexpr int K = RELAXED_TOPK;
-  const int col = blockIdx.x;
-  const int chunk = blockIdx.y;
   const int i0 = chunk * RELAXED_CHUNK;
   const int i1 = min(r, i0 + RELAXED_CHUNK);
   const double* colp = a21 + (size_t)col * lda;
@@ -191,17 +198,21 @@ __global__ __launch_bounds__(256) void relaxed_topk_kernel(int r, int p, const d
   }
 }
 
+__global__ __launch_bounds__(256) void relaxed_topk_kernel(int r, int p, const double* __restrict__ a21,
+                                                         int lda, int nchunks, Cand* __restrict__ cand,
+                                                         int* __restrict__ status) {
+  relaxed_topk_body(r, p, a21, lda, nchunks, cand, status, blockIdx.x, blockIdx.y);
+}
+
 // One workgroup of 1024 threads.  Dynamic LDS: final candidate lists
 // (p * K Cand) + chosen rows (p ints).
-__global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, const double* __restrict__ a21,
-                                                            int lda, int nchunks,
-                                                            const Cand* __restrict__ cand,
-                                                            double* __restrict__ c, int ldc,
-                                                            int* __restrict__ crow_out,
-                                                            int* __restrict__ status) {
+extern __shared__ unsigned char cmp_smem[];
+
+CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, int lda, int nchunks,
+                                 const Cand* __restrict__ cand, double* __restrict__ c, int ldc,
+                                 int* __restrict__ crow_out, int* __restrict__ status) {
   constexpr int K = RELAXED_TOPK;
-  extern __shared__ unsigned char smem[];
-  Cand* lists = reinterpret_cast<Cand*>(smem);
+  Cand* lists = reinterpret_cast<Cand*>(cmp_smem);
   int* chosen = reinterpret_cast<int*>(lists + (size_t)p * K);
   __shared__ int s_pick;
   __shared__ int s_need_scan;
@@ -315,6 +326,15 @@ __global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, cons
     for (int j = threadIdx.x; j < p; j += blockDim.x) crow_out[j] = chosen[j];
 }
 
+__global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, const double* __restrict__ a21,
+                                                            int lda, int nchunks,
+                                                            const Cand* __restrict__ cand,
+                                                            double* __restrict__ c, int ldc,
+                                                            int* __restrict__ crow_out,
+                                                            int* __restrict__ status) {
+  relaxed_select_body(r, p, a21, lda, nchunks, cand, c, ldc, crow_out, status);
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -365,6 +385,91 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
     }
   } else {
     return -5;
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+// ---------------------------------------------------------------------------
+// Batched compression: one grid over all supernodes of a batch (the node is
+// blockIdx.z, or blockIdx.x for the one-workgroup select), each node's A21
+// compressed into the C of its own workspace as by the single-node launches.
+// ---------------------------------------------------------------------------
+
+__global__ void batch_zero_c_kernel(const BatchNode* __restrict__ nodes, int method) {
+  const BatchNode& nd = nodes[blockIdx.y];
+  const Workspace ws = workspace_layout(nd.n, nd.p, method);
+  unsigned long long* c = reinterpret_cast<unsigned long long*>(nd.work + ws.c_off);
+  const int cnt = nd.p * nd.p;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < cnt; q += gridDim.x * blockDim.x) c[q] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void strict_rowset_batch_kernel(const BatchNode* __restrict__ nodes) {
+  const BatchNode& nd = nodes[blockIdx.y];
+  const int r = nd.n - nd.p;
+  const Workspace ws = workspace_layout(nd.n, nd.p, CTP_STRICT);
+  strict_rowset_body(r, nd.p, nd.a + nd.p, nd.lda, reinterpret_cast<int*>(nd.work + ws.j_off), nd.status,
+                     blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void strict_colmax_batch_kernel(const BatchNode* __restrict__ nodes) {
+  const BatchNode& nd = nodes[blockIdx.z];
+  const int r = nd.n - nd.p;
+  if ((int)blockIdx.x * STRICT_ROWS >= r || (int)blockIdx.y * STRICT_CG >= nd.p) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, CTP_STRICT);
+  strict_colmax_body(r, nd.p, nd.a + nd.p, nd.lda, reinterpret_cast<const int*>(nd.work + ws.j_off),
+                     reinterpret_cast<unsigned long long*>(nd.work + ws.c_off), nd.p, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void relaxed_topk_batch_kernel(const BatchNode* __restrict__ nodes) {
+  const BatchNode& nd = nodes[blockIdx.z];
+  const int r = nd.n - nd.p;
+  if (r <= 0 || (int)blockIdx.x >= nd.p || (int)blockIdx.y >= nd.nchunks) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, CTP_RELAXED);
+  relaxed_topk_body(r, nd.p, nd.a + nd.p, nd.lda, nd.nchunks, reinterpret_cast<Cand*>(nd.work + ws.cand_off),
+                    nd.status, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(1024) void relaxed_select_batch_kernel(const BatchNode* __restrict__ nodes) {
+  const BatchNode& nd = nodes[blockIdx.x];
+  const int r = nd.n - nd.p;
+  const Workspace ws = workspace_layout(nd.n, nd.p, CTP_RELAXED);
+  double* c = reinterpret_cast<double*>(nd.work + ws.c_off);
+  int* crow = reinterpret_cast<int*>(nd.work + ws.crow_off);
+  if (r > 0) {
+    relaxed_select_body(r, nd.p, nd.a + nd.p, nd.lda, nd.nchunks, reinterpret_cast<const Cand*>(nd.work + ws.cand_off),
+                        c, nd.p, crow, nd.status);
+  } else {
+    for (int q = threadIdx.x; q < nd.p * nd.p; q += blockDim.x) c[q] = 0.0;
+    for (int j = threadIdx.x; j < nd.p; j += blockDim.x) crow[j] = -1;
+  }
+}
+
+int launch_compress_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int max_chunks,
+                          hipStream_t stream) {
+  if (count <= 0) return 0;
+  if (method == CTP_STRICT) {
+    batch_zero_c_kernel<<<dim3(16, count), 256, 0, stream>>>(nodes, method);
+    if (max_r > 0) {
+      strict_rowset_batch_kernel<<<dim3((max_r + 255) / 256, count), 256, 0, stream>>>(nodes);
+      const size_t lds = (size_t)max_p * STRICT_CG * sizeof(unsigned long long);
+      if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)strict_colmax_batch_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+      }
+      strict_colmax_batch_kernel<<<dim3((max_r + STRICT_ROWS - 1) / STRICT_ROWS, (max_p + STRICT_CG - 1) / STRICT_CG,
+                                        count), 256, lds, stream>>>(nodes);
+    }
+  } else if (method == CTP_RELAXED) {
+    if (max_r > 0) relaxed_topk_batch_kernel<<<dim3(max_p, max_chunks, count), 256, 0, stream>>>(nodes);
+    const size_t lds = (size_t)max_p * RELAXED_TOPK * sizeof(Cand) + (size_t)max_p * sizeof(int);
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)relaxed_select_batch_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+    }
+    relaxed_select_batch_kernel<<<count, 1024, lds, stream>>>(nodes);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;

@@ -1,0 +1,658 @@
+// Dense symmetric indefinite LDL^T built from supernode panels, the solve
+// with its factors and FP64 iterative refinement.
+//
+// Section 1 describes a multifrontal code: each supernode is factorized
+// (Factor), its block of L below the pivots is solved for (Solve), the
+// Schur complement is formed for the parent (Form), failed pivots are
+// delayed to the parent, and the root eliminates everything.  A dense
+// matrix factorized right-looking in panels of pw columns is that chain
+// with one child per node:
+//   panel = delayed columns of the previous panel + the next pw columns,
+//           every row below them;
+//   Factor + Solve on the panel with the chosen pivot rule (the supernode
+//   entry points), the panel's interchanges applied to the rows of the L
+//   columns already done and composed into one global permutation;
+//   trailing matrix -= L21 W^T (Form, subtracted), W = L21 D;
+//   the last panel (no rows below) eliminates every column (CTP_FLAG_ROOT).
+// The host reads back nelim after each panel (panel widths depend on it).
+//
+// Reduced precision (ctp_opts.prec 1 / 2): the trailing matrix lives in an
+// FP32 copy, the trailing update runs on FP32 / BF16 matrix cores with FP32
+// accumulation, while the panels (pivot search, 2x2 inverses, L21, W) are
+// computed in FP64 from the FP32 trailing values.  The solve uses the FP64
+// factors; refinement computes residuals with the original FP64 matrix.
+//
+// Solve with the factors, P A P^T = L D L^T:
+//   y = P b;  L y' = y (forward);  z = D^-1 y';  L^T x' = z (backward);
+//   x = P^T x'.
+// The diagonal blocks of L (DB = 128 columns) are inverted once at the end
+// of the factorization and L^T is mirrored into the upper triangle, so each
+// block step of either sweep is a dense product with coalesced columns:
+//   forward  block j: z_j = Linv_j y_j; rows below: y_R -= L(R, j) z_j
+//   backward block j: x_j = Linv_j^T z_j; rows above: z_R -= L^T(R, j) x_j
+// (one launch per block, every workgroup recomputing the small product).
+
+#include <vector>
+
+#include "common.h"
+
+namespace ctp {
+
+int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, int ldw,
+                       const int* nelim, double* c, int ldc, hipStream_t stream);
+int launch_lowp_update(int r, int K, const double* l21, int lda, const double* w, int ldw,
+                       const int* nelim, float* c, int ldc, int prec, void* ops, hipStream_t stream);
+size_t lowp_ops_bytes(int r, int kmax);
+
+constexpr int DB = 128;   // diagonal block of the solve
+
+// ---------------------------------------------------------------------------
+// panel bookkeeping
+// ---------------------------------------------------------------------------
+
+// Rows k0..k0+pe-1 of the L columns 0..k0-1 follow the panel's interchanges:
+// new row q = old row perm_p[q].  One workgroup per column.
+__global__ __launch_bounds__(256) void dense_perm_left_kernel(double* a, int lda, int k0, int pe,
+                                                              const int* __restrict__ perm_p) {
+  __shared__ double col[CTP_MAX_P];
+  double* c = a + (size_t)blockIdx.x * lda + k0;
+  for (int q = threadIdx.x; q < pe; q += blockDim.x) col[q] = c[perm_p[q]];
+  __syncthreads();
+  for (int q = threadIdx.x; q < pe; q += blockDim.x) c[q] = col[q];
+}
+
+// Global permutation, pivot types and D of the panel's eliminated columns.
+__global__ __launch_bounds__(512) void dense_bookkeep_kernel(int k0, int pe, const int* __restrict__ perm_p,
+                                                             const int* __restrict__ piv_p,
+                                                             const double* __restrict__ d_p,
+                                                             const int* __restrict__ nelim_p, int* gperm,
+                                                             int* gpiv, double* gd) {
+  __shared__ int old[CTP_MAX_P];
+  const int ne = min(max(*nelim_p, 0), pe);
+  for (int q = threadIdx.x; q < pe; q += blockDim.x) old[q] = gperm[k0 + q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < pe; q += blockDim.x) gperm[k0 + q] = old[perm_p[q]];
+  for (int q = threadIdx.x; q < ne; q += blockDim.x) {
+    gpiv[k0 + q] = piv_p[q];
+    gd[2 * (k0 + q)] = d_p[2 * q];
+    gd[2 * (k0 + q) + 1] = d_p[2 * q + 1];
+  }
+}
+
+__global__ void dense_iota_kernel(int* gperm, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) gperm[i] = i;
+}
+
+// FP32 working copy of the lower triangle (columns j, rows j..N-1).
+__global__ __launch_bounds__(256) void dense_to_f32_kernel(const double* __restrict__ a, int lda,
+                                                           float* __restrict__ w32, int ld32, int N) {
+  const int j = blockIdx.y;
+  for (int i = j + blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256)
+    w32[(size_t)j * ld32 + i] = (float)a[(size_t)j * lda + i];
+}
+
+// Panel columns c0..c1-1, rows c0..N-1, from the FP32 working copy.
+__global__ __launch_bounds__(256) void dense_from_f32_kernel(double* __restrict__ a, int lda,
+                                                             const float* __restrict__ w32, int ld32,
+                                                             int c0, int N) {
+  const int j = c0 + blockIdx.y;
+  for (int i = j + blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256)
+    a[(size_t)j * lda + i] = (double)w32[(size_t)j * ld32 + i];
+}
+
+// ---------------------------------------------------------------------------
+// solve preparation: L^T into the upper triangle, inverses of the diagonal
+// blocks of the unit lower L (entries that hold D are read as 0 / 1)
+// ---------------------------------------------------------------------------
+
+CTP_DEV double l_entry(const double* a, int lda, const int* piv, int i, int k) {
+  // L(i, k) of the unit lower factor, i > k
+  if (i == k + 1 && piv[k] == PIV_2X2_FIRST) return 0.0;
+  return a[(size_t)k * lda + i];
+}
+
+// U(k, i) = L(i, k) for i > k, stored at row k, column i (upper triangle).
+__global__ __launch_bounds__(256) void dense_mirror_kernel(double* a, int lda, const int* __restrict__ piv,
+                                                           int N) {
+  // 32 x 32 tiles of the strictly lower triangle, transposed through LDS
+  __shared__ double t[32][33];
+  const int bi = blockIdx.x, bk = blockIdx.y;   // tile row (i), tile column (k)
+  if (bi < bk) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows of threads
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = bi * 32 + tx, k = bk * 32 + yy;
+    double v = 0.0;
+    if (i < N && k < N && i > k) v = l_entry(a, lda, piv, i, k);
+    t[yy][tx] = v;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int k = bk * 32 + tx, i = bi * 32 + yy;   // write U(k, i) at row k, column i
+    if (i < N && k < N && i > k) a[(size_t)i * lda + k] = t[tx][yy];
+  }
+}
+
+// Inverse of the unit lower diagonal block b (columns b*DB ..): each thread
+// owns one column j of X = L_bb^-1 and runs the forward substitution for
+// it, X(i, j) = -sum_{j <= k < i} L(i, k) X(k, j), the column kept in LDS.
+extern __shared__ double dn_dyn[];
+constexpr int LINV_LDS = DB * (DB + 1) * (int)sizeof(double);
+
+__global__ __launch_bounds__(DB) void dense_linv_kernel(const double* __restrict__ a, int lda,
+                                                        const int* __restrict__ piv, int N,
+                                                        double* __restrict__ linv, double* __restrict__ linvt) {
+  double (*X)[DB + 1] = reinterpret_cast<double (*)[DB + 1]>(dn_dyn);
+  const int b = blockIdx.x;
+  const int c0 = b * DB;
+  const int nb = min(DB, N - c0);
+  const int j = threadIdx.x;
+  for (int i = 0; i < DB; ++i) X[i][j] = 0.0;
+  if (j < nb) {
+    X[j][j] = 1.0;
+    for (int i = j + 1; i < nb; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s = fma(l_entry(a, lda, piv, c0 + i, c0 + k), X[k][j], s);
+      X[i][j] = -s;
+    }
+  }
+  __syncthreads();
+  double* L = linv + (size_t)b * DB * DB;
+  double* LT = linvt + (size_t)b * DB * DB;
+  for (int i = 0; i < DB; ++i) {
+    L[(size_t)j * DB + i] = X[i][j];     // column-major Linv
+    LT[(size_t)i * DB + j] = X[i][j];    // column-major Linv^T
+  }
+}
+
+// ---------------------------------------------------------------------------
+// solve sweeps
+// ---------------------------------------------------------------------------
+
+// y (N x nrhs, ldy) <- P b
+__global__ void dense_gather_kernel(const double* __restrict__ b, int ldb, const int* __restrict__ perm,
+                                    double* __restrict__ y, int ldy, int N, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < N && c < nrhs) y[(size_t)c * ldy + i] = b[(size_t)c * ldb + perm[i]];
+}
+
+// x <- P^T y
+__global__ void dense_scatter_kernel(const double* __restrict__ y, int ldy, const int* __restrict__ perm,
+                                     double* __restrict__ x, int ldx, int N, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < N && c < nrhs) x[(size_t)c * ldx + perm[i]] = y[(size_t)c * ldy + i];
+}
+
+// z <- D^-1 y (1x1 and 2x2 blocks; a zero pivot gives 0)
+__global__ void dense_dsolve_kernel(const int* __restrict__ piv, const double* __restrict__ d,
+                                    double* __restrict__ y, int ldy, int N, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= N || c >= nrhs) return;
+  double* yc = y + (size_t)c * ldy;
+  const int pt = piv[i];
+  if (pt == PIV_2X2_FIRST) {
+    const double a11 = d[2 * i], a21 = d[2 * i + 1], a22 = d[2 * i + 2];
+    const double s = 1.0 / fmax(fmax(fabs(a11), fabs(a21)), fabs(a22));
+    const double det = (a22 * s) * a11 - (a21 * s) * a21;
+    const double f = s / det;
+    const double y1 = yc[i], y2 = yc[i + 1];
+    yc[i] = (f * a22) * y1 - (f * a21) * y2;
+    yc[i + 1] = -(f * a21) * y1 + (f * a11) * y2;
+  } else if (pt == PIV_1X1) {
+    yc[i] = yc[i] / d[2 * i];
+  } else if (pt == PIV_ZERO) {
+    yc[i] = 0.0;
+  }
+}
+
+constexpr int SW_THREADS = 256;
+constexpr int SW_MAXRHS = 16;
+
+// One block step of a sweep.  blk: the diagonal block; the DB x DB inverse
+// M (column-major, applied as t = M v_blk); rows of the update: the
+// DB-row chunks listed by the grid (workgroup 0 writes t back into v_blk,
+// workgroup q >= 1 updates chunk rlo + (q-1)*DB of v with the off-diagonal
+// block of F, whose column k of the block sits at F + (c0 + k) * ldf).
+// piv (forward sweep only, else null): a 2x2 pivot that straddles the
+// block boundary keeps the off-diagonal of D in L(c0 + nb, c0 + nb - 1);
+// that entry is read as 0.
+__global__ __launch_bounds__(SW_THREADS) void dense_sweep_kernel(const double* __restrict__ F, int ldf,
+                                                                 const double* __restrict__ M, int c0,
+                                                                 int nb, int rlo, int rhi,
+                                                                 const int* __restrict__ piv,
+                                                                 double* __restrict__ v, int ldv,
+                                                                 int nrhs) {
+  __shared__ double vb[SW_MAXRHS][DB];
+  __shared__ double tb[SW_MAXRHS][DB];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < nrhs * DB; q += SW_THREADS) {
+    const int c = q / DB, k = q % DB;
+    vb[c][k] = k < nb ? v[(size_t)c * ldv + c0 + k] : 0.0;
+  }
+  __syncthreads();
+  // t = M vb (rows i < nb)
+  for (int q = tid; q < nrhs * DB; q += SW_THREADS) {
+    const int c = q / DB, i = q % DB;
+    double s = 0.0;
+    if (i < nb)
+      for (int k = 0; k < nb; ++k) s = fma(M[(size_t)k * DB + i], vb[c][k], s);
+    tb[c][i] = s;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int q = tid; q < nrhs * DB; q += SW_THREADS) {
+      const int c = q / DB, i = q % DB;
+      if (i < nb) v[(size_t)c * ldv + c0 + i] = tb[c][i];
+    }
+    return;
+  }
+  const int r0 = rlo + (blockIdx.x - 1) * DB;
+  const int i = r0 + (tid % DB);
+  if (i >= rhi) return;
+  const int kend = (piv && i == c0 + nb && piv[c0 + nb - 1] == PIV_2X2_FIRST) ? nb - 1 : nb;
+  for (int c = tid / DB; c < nrhs; c += SW_THREADS / DB) {
+    double s = 0.0;
+    for (int k = 0; k < kend; ++k) s = fma(F[(size_t)(c0 + k) * ldf + i], tb[c][k], s);
+    v[(size_t)c * ldv + i] -= s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// refinement: residual r = b - A x and the norms of the backward error
+// ---------------------------------------------------------------------------
+
+// r <- r - A(rows, cols) x(cols) for a 256-row stripe and a 512-column
+// chunk (r starts as b); arow accumulates the absolute row sums of A.
+constexpr int RES_ROWS = 256, RES_COLS = 512;
+
+__global__ __launch_bounds__(RES_ROWS) void dense_residual_kernel(const double* __restrict__ A, int lda,
+                                                                  const double* __restrict__ x, int ldx,
+                                                                  double* __restrict__ r, int ldr, int N,
+                                                                  int nrhs, double* __restrict__ arow) {
+  __shared__ double xs[SW_MAXRHS][RES_COLS];
+  const int j0 = blockIdx.y * RES_COLS;
+  const int j1 = min(N, j0 + RES_COLS);
+  for (int q = threadIdx.x; q < nrhs * RES_COLS; q += RES_ROWS) {
+    const int c = q / RES_COLS, jj = q % RES_COLS;
+    xs[c][jj] = j0 + jj < N ? x[(size_t)c * ldx + j0 + jj] : 0.0;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * RES_ROWS + threadIdx.x;
+  if (i >= N) return;
+  double acc[SW_MAXRHS];
+  for (int c = 0; c < SW_MAXRHS; ++c) acc[c] = 0.0;
+  double as = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    const double aij = A[(size_t)j * lda + i];
+    as += fabs(aij);
+#pragma unroll
+    for (int c = 0; c < SW_MAXRHS; ++c)
+      if (c < nrhs) acc[c] = fma(aij, xs[c][j - j0], acc[c]);
+  }
+  if (arow) atomicAdd(arow + i, as);
+  for (int c = 0; c < nrhs; ++c) atomicAdd(r + (size_t)c * ldr + i, -acc[c]);
+}
+
+CTP_DEV void atomic_max_nonneg(double* p, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// norms: [0] ||A||_inf, then per column c: [1+c] ||r||, [1+nrhs+c] ||x||, [1+2nrhs+c] ||b||
+__global__ __launch_bounds__(256) void dense_norms_kernel(const double* __restrict__ arow,
+                                                          const double* __restrict__ r, int ldr,
+                                                          const double* __restrict__ x, int ldx,
+                                                          const double* __restrict__ b, int ldb, int N,
+                                                          int nrhs, double* norms) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  double va = 0.0;
+  double vr[SW_MAXRHS], vx[SW_MAXRHS], vb[SW_MAXRHS];
+  for (int c = 0; c < SW_MAXRHS; ++c) vr[c] = vx[c] = vb[c] = 0.0;
+  if (i < N) {
+    va = arow[i];
+    for (int c = 0; c < nrhs; ++c) {
+      vr[c] = fabs(r[(size_t)c * ldr + i]);
+      vx[c] = fabs(x[(size_t)c * ldx + i]);
+      vb[c] = fabs(b[(size_t)c * ldb + i]);
+    }
+  }
+  va = wave_max(va);
+  for (int c = 0; c < nrhs; ++c) {
+    vr[c] = wave_max(vr[c]);
+    vx[c] = wave_max(vx[c]);
+    vb[c] = wave_max(vb[c]);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(norms, va);
+    for (int c = 0; c < nrhs; ++c) {
+      atomic_max_nonneg(norms + 1 + c, vr[c]);
+      atomic_max_nonneg(norms + 1 + nrhs + c, vx[c]);
+      atomic_max_nonneg(norms + 1 + 2 * nrhs + c, vb[c]);
+    }
+  }
+}
+
+__global__ void dense_copy_kernel(double* __restrict__ dst, int ldd, const double* __restrict__ src, int lds,
+                                  int N, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < N && c < nrhs) dst[(size_t)c * ldd + i] = src[(size_t)c * lds + i];
+}
+
+__global__ void dense_fill_kernel(double* p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void dense_axpy_kernel(double* __restrict__ x, int ldx, const double* __restrict__ dx, int lddx,
+                                  int N, int nrhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < N && c < nrhs) x[(size_t)c * ldx + i] += dx[(size_t)c * lddx + i];
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of x = A^-1 b for symmetric A:  bbar = A^-1 xbar (the same
+// factors), Abar = -sum_c (bbar_c x_c^T + x_c bbar_c^T) / 2, full N x N
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void dense_sym_outer_kernel(const double* __restrict__ bbar, int ldb,
+                                                              const double* __restrict__ x, int ldx, int N,
+                                                              int nrhs, double* __restrict__ abar, int ldg) {
+  __shared__ double bj[SW_MAXRHS], xj[SW_MAXRHS];
+  const int j = blockIdx.y;
+  if (threadIdx.x < nrhs) {
+    bj[threadIdx.x] = bbar[(size_t)threadIdx.x * ldb + j];
+    xj[threadIdx.x] = x[(size_t)threadIdx.x * ldx + j];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  // both products rounded before the sum, so that entries (i, j) and
+  // (j, i) are the same two numbers added (Abar exactly symmetric)
+  double s = 0.0;
+  for (int c = 0; c < nrhs; ++c) {
+    const double t1 = __dmul_rn(bbar[(size_t)c * ldb + i], xj[c]);
+    const double t2 = __dmul_rn(x[(size_t)c * ldx + i], bj[c]);
+    s = __dadd_rn(s, __dadd_rn(t1, t2));
+  }
+  abar[(size_t)j * ldg + i] = -0.5 * s;
+}
+
+// ---------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------
+
+struct DenseWork {
+  size_t sn_off = 0, sn_bytes = 0;     // supernode workspace (largest panel)
+  size_t pperm_off = 0, ppiv_off = 0, pd_off = 0, pnelim_off = 0, pstatus_off = 0;
+  size_t linv_off = 0, linvt_off = 0;  // inverses of the diagonal blocks
+  size_t w32_off = 0;                  // FP32 trailing matrix (reduced precision)
+  int ld32 = 0;
+  size_t ops_off = 0;                  // low-precision operands of the trailing update
+  size_t y_off = 0;                    // solve / refinement vectors
+  size_t arow_off = 0;                 // absolute row sums of A (refinement)
+  size_t norms_off = 0;
+  size_t total = 0;
+};
+
+static int dense_nblocks(int N) { return (N + DB - 1) / DB; }
+
+static DenseWork dense_layout(int N, int pw, const ctp_opts* o, int nrhs_max) {
+  DenseWork w;
+  size_t off = 0;
+  ctp_opts so = *o;
+  size_t sn = 0;
+  const int pmax = CTP_MAX_P < N ? CTP_MAX_P : N;
+  // every term of the supernode workspace grows with n and p except the W
+  // buffer ((n - p) x p): the size at (2N, pmax) bounds every panel shape
+  ctp_workspace_size(2 * N, pmax, &so, &sn);
+  w.sn_off = off;
+  w.sn_bytes = sn;
+  off = align_up(off + sn, 256);
+  w.pperm_off = off; off = align_up(off + CTP_MAX_P * sizeof(int), 256);
+  w.ppiv_off = off; off = align_up(off + CTP_MAX_P * sizeof(int), 256);
+  w.pd_off = off; off = align_up(off + 2 * CTP_MAX_P * sizeof(double), 256);
+  w.pnelim_off = off; off = align_up(off + sizeof(int), 256);
+  w.pstatus_off = off; off = align_up(off + sizeof(int), 256);
+  const size_t nbk = (size_t)dense_nblocks(N);
+  w.linv_off = off; off = align_up(off + nbk * DB * DB * sizeof(double), 256);
+  w.linvt_off = off; off = align_up(off + nbk * DB * DB * sizeof(double), 256);
+  if (o->prec != 0) {
+    w.ld32 = (int)align_up((size_t)N, 64);
+    w.w32_off = off; off = align_up(off + (size_t)w.ld32 * N * sizeof(float), 256);
+    w.ops_off = off; off = align_up(off + lowp_ops_bytes(N, pmax), 256);
+  }
+  w.y_off = off; off = align_up(off + (size_t)2 * N * (nrhs_max > 0 ? nrhs_max : 1) * sizeof(double), 256);
+  w.arow_off = off; off = align_up(off + (size_t)(N > 0 ? N : 1) * sizeof(double), 256);
+  w.norms_off = off; off = align_up(off + (1 + 3 * SW_MAXRHS) * sizeof(double), 256);
+  w.total = off;
+  (void)pw;
+  return w;
+}
+
+}  // namespace ctp
+
+using namespace ctp;
+
+static int dense_check(int N, int pw, const double* a, int lda, const ctp_opts* opts) {
+  if (N < 0) return -1;
+  if (pw < 1 || pw > CTP_MAX_P) return -2;
+  if (!a && N > 0) return -3;
+  if (lda < (N > 1 ? N : 1)) return -4;
+  if (!opts || opts->prec < 0 || opts->prec > 2) return -5;
+  return 0;
+}
+
+extern "C" {
+
+int ctp_dense_workspace_size(int N, int pw, const ctp_opts* opts, int nrhs_max, size_t* bytes) {
+  if (N < 0) return -1;
+  if (pw < 1 || pw > CTP_MAX_P) return -2;
+  if (!opts || opts->prec < 0 || opts->prec > 2) return -3;
+  if (nrhs_max < 0 || nrhs_max > SW_MAXRHS) return -4;
+  if (!bytes) return -5;
+  *bytes = dense_layout(N, pw, opts, nrhs_max).total;
+  return 0;
+}
+
+int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                   double* d, int* status, int* npanels, void* work, size_t lwork, hipStream_t stream) {
+  int rc = dense_check(N, pw, a, lda, opts);
+  if (rc) return rc;
+  if (N > 0 && (!perm || !piv || !d)) return -6;
+  if (!status) return -9;
+  DenseWork L = dense_layout(N, pw, opts, 0);
+  if (!work || lwork < L.total) return -12;
+  if (N == 0) return 0;
+  unsigned char* base = static_cast<unsigned char*>(work);
+  void* sn = base + L.sn_off;
+  int* pperm = reinterpret_cast<int*>(base + L.pperm_off);
+  int* ppiv = reinterpret_cast<int*>(base + L.ppiv_off);
+  double* pd = reinterpret_cast<double*>(base + L.pd_off);
+  int* pnelim = reinterpret_cast<int*>(base + L.pnelim_off);
+  int* pstatus = reinterpret_cast<int*>(base + L.pstatus_off);
+  float* w32 = reinterpret_cast<float*>(base + L.w32_off);
+  const bool lowp = opts->prec != 0;
+
+  dense_iota_kernel<<<(N + 255) / 256, 256, 0, stream>>>(perm, N);
+  if (lowp) dense_to_f32_kernel<<<dim3(4, N), 256, 0, stream>>>(a, lda, w32, L.ld32, N);
+
+  ctp_opts po = *opts;
+  int k0 = 0, width = pw < N ? pw : N, carried = 0, panels = 0;
+  int acc_status = 0;
+  while (k0 < N) {
+    if (width > CTP_MAX_P) return -900;   // delays grew a panel past CTP_MAX_P
+    const int n = N - k0;
+    const bool root = n == width;
+    double* ap = a + (size_t)k0 * lda + k0;
+    // reduced precision: the new columns of the panel come from the FP32 copy
+    if (lowp && width > carried)
+      dense_from_f32_kernel<<<dim3(4, width - carried), 256, 0, stream>>>(a, lda, w32, L.ld32, k0 + carried, N);
+    po.flags = opts->flags | (root ? CTP_FLAG_ROOT : 0u);
+    rc = ctp_supernode(n, width, ap, lda, &po, pperm, ppiv, pd, pnelim, pstatus, sn, L.sn_bytes, stream);
+    if (rc) return rc;
+    if (k0 > 0) dense_perm_left_kernel<<<k0, 256, 0, stream>>>(a, lda, k0, width, pperm);
+    dense_bookkeep_kernel<<<1, 512, 0, stream>>>(k0, width, pperm, ppiv, pd, pnelim, perm, piv, d);
+    int ne = 0, st = 0;
+    if (hipMemcpyAsync(&ne, pnelim, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(&st, pstatus, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+    acc_status |= st;
+    ++panels;
+    if (n > width && ne > 0) {
+      // the W = L21 D that the solve left in the supernode workspace
+      Workspace ws = workspace_layout(n, width, po.method);
+      const double* w = reinterpret_cast<const double*>(static_cast<unsigned char*>(sn) + ws.w_off);
+      if (!lowp) {
+        rc = launch_schur_w_sub(n, width, ap, lda, w, ws.ldw, pnelim,
+                                a + (size_t)(k0 + width) * lda + (k0 + width), lda, stream);
+      } else {
+        rc = launch_lowp_update(n - width, ne, ap + width, lda, w, ws.ldw, pnelim,
+                                w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width), L.ld32, opts->prec,
+                                base + L.ops_off, stream);
+      }
+      if (rc) return rc;
+    }
+    carried = width - ne;
+    k0 += ne;
+    width = N - k0 < carried + pw ? N - k0 : carried + pw;
+  }
+  // solve preparation
+  {
+    dim3 mg(dense_nblocks(N) * (DB / 32), dense_nblocks(N) * (DB / 32));
+    dense_mirror_kernel<<<mg, 256, 0, stream>>>(a, lda, piv, N);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(dense_linv_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, LINV_LDS);
+    dense_linv_kernel<<<dense_nblocks(N), DB, LINV_LDS, stream>>>(a, lda, piv, N,
+                                                          reinterpret_cast<double*>(base + L.linv_off),
+                                                          reinterpret_cast<double*>(base + L.linvt_off));
+  }
+  int* st_out = status;
+  hipMemcpyAsync(st_out, &acc_status, sizeof(int), hipMemcpyHostToDevice, stream);
+  if (hipStreamSynchronize(stream) != hipSuccess) return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+  if (npanels) *npanels = panels;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int ctp_ldlt_solve(int N, int nrhs, const double* a, int lda, const int* perm, const int* piv,
+                   const double* d, double* b, int ldb, const ctp_opts* opts, int pw, void* work,
+                   size_t lwork, hipStream_t stream) {
+  if (N < 0) return -1;
+  if (nrhs < 0 || nrhs > SW_MAXRHS) return -2;
+  if (!a && N > 0) return -3;
+  if (lda < (N > 1 ? N : 1)) return -4;
+  if (N > 0 && (!perm || !piv || !d)) return -5;
+  if (!b && N > 0 && nrhs > 0) return -8;
+  if (ldb < (N > 1 ? N : 1)) return -9;
+  if (!opts || opts->prec < 0 || opts->prec > 2) return -10;
+  if (pw < 1 || pw > CTP_MAX_P) return -11;
+  DenseWork L = dense_layout(N, pw, opts, nrhs);
+  if (!work || lwork < L.total) return -13;
+  if (N == 0 || nrhs == 0) return 0;
+  unsigned char* base = static_cast<unsigned char*>(work);
+  double* y = reinterpret_cast<double*>(base + L.y_off);
+  const int ldy = N;
+  const double* linv = reinterpret_cast<const double*>(base + L.linv_off);
+  const double* linvt = reinterpret_cast<const double*>(base + L.linvt_off);
+  const dim3 eg((N + 255) / 256, nrhs);
+  dense_gather_kernel<<<eg, 256, 0, stream>>>(b, ldb, perm, y, ldy, N, nrhs);
+  const int nbk = dense_nblocks(N);
+  for (int j = 0; j < nbk; ++j) {          // forward: L y' = y
+    const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
+    const int rlo = c0 + nb, rhi = N;
+    const int chunks = (rhi - rlo + DB - 1) / DB;
+    dense_sweep_kernel<<<1 + chunks, SW_THREADS, 0, stream>>>(a, lda, linv + (size_t)j * DB * DB, c0, nb,
+                                                              rlo, rhi, piv, y, ldy, nrhs);
+  }
+  dense_dsolve_kernel<<<eg, 256, 0, stream>>>(piv, d, y, ldy, N, nrhs);
+  for (int j = nbk - 1; j >= 0; --j) {     // backward: L^T x' = z, L^T in the upper triangle
+    const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
+    const int rlo = 0, rhi = c0;
+    const int chunks = (rhi - rlo + DB - 1) / DB;
+    dense_sweep_kernel<<<1 + chunks, SW_THREADS, 0, stream>>>(a, lda, linvt + (size_t)j * DB * DB, c0, nb,
+                                                              rlo, rhi, nullptr, y, ldy, nrhs);
+  }
+  dense_scatter_kernel<<<eg, 256, 0, stream>>>(y, ldy, perm, b, ldb, N, nrhs);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int ctp_ldlt_refine(int N, int nrhs, const double* a0, int lda0, const double* f, int ldf,
+                    const int* perm, const int* piv, const double* d, const double* b, int ldb,
+                    double* x, int ldx, const ctp_opts* opts, int pw, double tol, int max_steps,
+                    int* steps, double* bwd_hist, void* work, size_t lwork, hipStream_t stream) {
+  if (N < 0) return -1;
+  if (nrhs < 1 || nrhs > SW_MAXRHS) return -2;
+  if (!a0 || lda0 < (N > 1 ? N : 1)) return -3;
+  if (!f || ldf < (N > 1 ? N : 1)) return -5;
+  if (!b || ldb < (N > 1 ? N : 1)) return -10;
+  if (!x || ldx < (N > 1 ? N : 1)) return -12;
+  if (!opts) return -14;
+  if (max_steps < 0) return -17;
+  DenseWork L = dense_layout(N, pw, opts, nrhs);
+  if (!work || lwork < L.total) return -20;
+  if (N == 0) return 0;
+  unsigned char* base = static_cast<unsigned char*>(work);
+  double* r = reinterpret_cast<double*>(base + L.y_off) + (size_t)N * nrhs;   // second half of y
+  double* arow = reinterpret_cast<double*>(base + L.arow_off);
+  double* norms = reinterpret_cast<double*>(base + L.norms_off);
+  const int nn = 1 + 3 * nrhs;
+  const dim3 eg((N + 255) / 256, nrhs);
+  const dim3 rg((N + RES_ROWS - 1) / RES_ROWS, (N + RES_COLS - 1) / RES_COLS);
+  // x = solve(b)
+  dense_copy_kernel<<<eg, 256, 0, stream>>>(x, ldx, b, ldb, N, nrhs);
+  int rc = ctp_ldlt_solve(N, nrhs, f, ldf, perm, piv, d, x, ldx, opts, pw, work, lwork, stream);
+  if (rc) return rc;
+  std::vector<double> hn(nn);
+  int k = 0;
+  for (;;) {
+    // r = b - A x (the row sums of |A| on the first pass), then the norms
+    dense_copy_kernel<<<eg, 256, 0, stream>>>(r, N, b, ldb, N, nrhs);
+    if (k == 0) dense_fill_kernel<<<(N + 255) / 256, 256, 0, stream>>>(arow, N, 0.0);
+    dense_residual_kernel<<<rg, RES_ROWS, 0, stream>>>(a0, lda0, x, ldx, r, N, N, nrhs, k == 0 ? arow : nullptr);
+    dense_fill_kernel<<<1, 64, 0, stream>>>(norms, nn, 0.0);
+    dense_norms_kernel<<<(N + 255) / 256, 256, 0, stream>>>(arow, r, N, x, ldx, b, ldb, N, nrhs, norms);
+    if (hipMemcpyAsync(hn.data(), norms, nn * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+    double be = 0.0;
+    for (int c = 0; c < nrhs; ++c) {
+      const double den = hn[0] * hn[1 + nrhs + c] + hn[1 + 2 * nrhs + c];
+      const double v = den > 0.0 ? hn[1 + c] / den : 0.0;
+      be = v > be ? v : be;
+    }
+    if (bwd_hist) bwd_hist[k] = be;
+    if (be <= tol || k >= max_steps) break;
+    rc = ctp_ldlt_solve(N, nrhs, f, ldf, perm, piv, d, r, N, opts, pw, work, lwork, stream);
+    if (rc) return rc;
+    dense_axpy_kernel<<<eg, 256, 0, stream>>>(x, ldx, r, N, N, nrhs);
+    ++k;
+  }
+  if (steps) *steps = k;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int ctp_ldlt_adjoint(int N, int nrhs, const double* a, int lda, const int* perm, const int* piv,
+                     const double* d, const double* x, int ldx, double* xbar, int ldxb, double* abar,
+                     int ldg, const ctp_opts* opts, int pw, void* work, size_t lwork, hipStream_t stream) {
+  if (N < 0) return -1;
+  if (nrhs < 0 || nrhs > SW_MAXRHS) return -2;
+  if (!x || ldx < (N > 1 ? N : 1)) return -8;
+  if (!xbar || ldxb < (N > 1 ? N : 1)) return -10;
+  if (!abar || ldg < (N > 1 ? N : 1)) return -12;
+  if (N == 0 || nrhs == 0) return 0;
+  // bbar = A^-1 xbar (A symmetric: A^-T = A^-1), in place of xbar
+  int rc = ctp_ldlt_solve(N, nrhs, a, lda, perm, piv, d, xbar, ldxb, opts, pw, work, lwork, stream);
+  if (rc) return rc;
+  dense_sym_outer_kernel<<<dim3((N + 255) / 256, N), 256, 0, stream>>>(xbar, ldxb, x, ldx, N, nrhs, abar, ldg);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+}  // extern "C"

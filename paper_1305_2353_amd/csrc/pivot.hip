@@ -54,7 +54,7 @@ namespace ctp {
 
 constexpr int PIV_THREADS = 1024;
 constexpr int PIV_WAVES = PIV_THREADS / 64;
-constexpr int NSLOT = 8;           // pending eliminated columns per batch
+constexpr int NSLOT = PIV_NSLOT;   // pending eliminated columns per batch
 constexpr int RCACHE = 1024;       // R rows whose multipliers are cached in LDS
 constexpr int APPLY_TILE = 64;
 
@@ -73,6 +73,7 @@ struct PivotArgs {
   double* R;     // bottom block, column-major, ldr (may be null when r == 0)
   int ldr;
   int abs_update;   // 1: strict rule for R
+  int root;         // 1: eliminate every column (fallback when a pass stalls)
   double u, small;
   int* perm;
   int* piv;
@@ -83,17 +84,14 @@ struct PivotArgs {
   double* wbuf;  // NSLOT x p: the batch's w vectors for the apply kernel
 };
 
-int pivot_state_bytes() { return (int)align_up(sizeof(PivState), 256); }
-size_t pivot_wbuf_bytes(int p) { return align_up((size_t)NSLOT * (p > 0 ? p : 1) * sizeof(double), 256); }
+static_assert(sizeof(PivState) <= PIV_STATE_BYTES, "pivot state does not fit its workspace slot");
 
 // ---------------------------------------------------------------------------
 // init: reflect A11, reset the state and the outputs
 // ---------------------------------------------------------------------------
 
-__global__ void pivot_init_kernel(PivotArgs g) {
+CTP_DEV void pivot_init_body(const PivotArgs& g, size_t tid, size_t stride) {
   const int p = g.p;
-  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t q = tid; q < (size_t)p * p; q += stride) {
     const int i = (int)(q % p), j = (int)(q / p);
     if (i < j) CM(g.T, i, j, g.lda) = CM(g.T, j, i, g.lda);
@@ -114,6 +112,10 @@ __global__ void pivot_init_kernel(PivotArgs g) {
     st->status = 0;
     *g.nelim_out = 0;
   }
+}
+
+__global__ void pivot_init_kernel(PivotArgs g) {
+  pivot_init_body(g, (size_t)blockIdx.x * blockDim.x + threadIdx.x, (size_t)gridDim.x * blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -287,9 +289,21 @@ CTP_DEV void sym_swap(const PivotArgs& g, int a, int b) {
   __syncthreads();
 }
 
-enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT, ACT_PASS, ACT_STOP };
+enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT, ACT_PASS, ACT_STOP, ACT_FALLBACK };
 
-__global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) {
+// Non-singularity part of the 2x2 test alone (Section 2): the scaled
+// determinant is clear of cancellation and of small.
+CTP_DEV bool det_ok(double att, double atm, double amm, double small) {
+  const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
+  if (big < small) return false;
+  const double s = 1.0 / big;
+  const double det1 = (atm * s) * atm;
+  const double det0 = (amm * s) * att;
+  const double det = det0 - det1;
+  return fabs(det) > fmax(fmax(small, fabs(det0) / 2.0), fabs(det1) / 2.0);
+}
+
+CTP_DEV void pivot_decide_body(const PivotArgs& g) {
   DecideShared& sh = pv_sh;
   const int p = g.p;
   const int rc = min(g.r, RCACHE);
@@ -323,62 +337,88 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) 
     const int nelim = sh.nelim;
     const int m = sh.m;
     if (nelim >= p || batch_full) break;
+    int action = ACT_NONE;
+    int t = -1;
+    int mc = m;        // position the action applies to
+    bool fb = false;   // root fallback step
     if (m >= p) {
       __syncthreads();
       if (threadIdx.x == 0) {
-        if (!sh.progress) sh.action = ACT_STOP;
+        if (!sh.progress) sh.action = g.root ? ACT_FALLBACK : ACT_STOP;
         else { sh.action = ACT_PASS; sh.progress = 0; sh.m = nelim; }
       }
       __syncthreads();
       if (sh.action == ACT_STOP) break;
-      continue;
-    }
-    double maxm = block_max(col_partial(g, rc, nelim, m, m, m));
-    const double amm = lazy_a(g, m, m);
-    const double colmax = fmax(fabs(amm), maxm);
-    if (threadIdx.x == 0 && !isfinite(colmax)) sh.status |= ST_NONFINITE;
-    int action = ACT_NONE;
-    int t = -1;
-    if (colmax < g.small) {
-      action = ACT_ZERO;
-    } else if (m > nelim) {
-      double v = -1.0;
-      int idx = 0x7fffffff;
-      for (int j = nelim + threadIdx.x; j < m; j += PIV_THREADS) {
-        double x = fabs(lazy_a(g, m, j));
-        if (x != x) x = -0.5;   // NaN: loses to any number, keeps t a valid index
-        if (x > v) { v = x; idx = j; }
+      if (sh.action == ACT_PASS) continue;
+      // A pass without progress in the last panel: eliminate the column at
+      // nelim regardless of u (1x1 unless below small, else a 2x2 with the
+      // next column if its determinant is safely nonzero, else zero).
+      fb = true;
+      const int k = nelim;
+      const double akk = lazy_a(g, k, k);
+      if (fabs(akk) >= g.small) {
+        action = ACT_1X1;
+        mc = k;
+      } else if (k + 1 < p && det_ok(akk, lazy_a(g, k + 1, k), lazy_a(g, k + 1, k + 1), g.small)) {
+        action = ACT_2X2;
+        t = k;
+        mc = k + 1;
+      } else {
+        action = ACT_ZERO;
+        mc = k;
       }
-      t = block_argmax(v, idx);
-      double maxt = col_partial(g, rc, nelim, t, t, m);
-      double maxm2 = col_partial(g, rc, nelim, m, t, m);
-      block_max2(maxt, maxm2);
-      const double att = lazy_a(g, t, t), atm = lazy_a(g, m, t);
-      const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
-      bool ok = false;
-      if (!(big < g.small)) {
-        const double s = 1.0 / big;
-        const double det1 = (atm * s) * atm;
-        const double det0 = (amm * s) * att;
-        const double det = det0 - det1;
-        const double bound = fmax(fmax(g.small, fabs(det0) / 2.0), fabs(det1) / 2.0);
-        if (fabs(det) > bound) {
-          if (fmax(maxt, maxm2) < g.small) {
-            ok = true;
-          } else {
-            const double f = s / fabs(det);
-            const double gt = (f * fabs(amm)) * maxt + (f * fabs(atm)) * maxm2;
-            const double gm = (f * fabs(atm)) * maxt + (f * fabs(att)) * maxm2;
-            ok = (gt <= inv_u) && (gm <= inv_u);
+      if (threadIdx.x == 0) sh.status |= ST_ROOT_FALLBACK;
+    } else {
+      double maxm = block_max(col_partial(g, rc, nelim, m, m, m));
+      const double amm = lazy_a(g, m, m);
+      const double colmax = fmax(fabs(amm), maxm);
+      if (threadIdx.x == 0 && !isfinite(colmax)) sh.status |= ST_NONFINITE;
+      if (colmax < g.small) {
+        action = ACT_ZERO;
+      } else if (m > nelim) {
+        double v = -1.0;
+        int idx = 0x7fffffff;
+        for (int j = nelim + threadIdx.x; j < m; j += PIV_THREADS) {
+          double x = fabs(lazy_a(g, m, j));
+          if (x != x) x = -0.5;   // NaN: loses to any number, keeps t a valid index
+          if (x > v) { v = x; idx = j; }
+        }
+        t = block_argmax(v, idx);
+        double maxt = col_partial(g, rc, nelim, t, t, m);
+        double maxm2 = col_partial(g, rc, nelim, m, t, m);
+        block_max2(maxt, maxm2);
+        const double att = lazy_a(g, t, t), atm = lazy_a(g, m, t);
+        const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
+        bool ok = false;
+        if (!(big < g.small)) {
+          const double s = 1.0 / big;
+          const double det1 = (atm * s) * atm;
+          const double det0 = (amm * s) * att;
+          const double det = det0 - det1;
+          const double bound = fmax(fmax(g.small, fabs(det0) / 2.0), fabs(det1) / 2.0);
+          if (fabs(det) > bound) {
+            if (fmax(maxt, maxm2) < g.small) {
+              ok = true;
+            } else {
+              const double f = s / fabs(det);
+              const double gt = (f * fabs(amm)) * maxt + (f * fabs(atm)) * maxm2;
+              const double gm = (f * fabs(atm)) * maxt + (f * fabs(att)) * maxm2;
+              ok = (gt <= inv_u) && (gm <= inv_u);
+            }
           }
         }
+        if (ok) action = ACT_2X2;
       }
-      if (ok) action = ACT_2X2;
+      if (action == ACT_NONE) {
+        const double bound = g.u * maxm;
+        action = (fabs(amm) >= bound) ? ACT_1X1 : ACT_REJECT;
+      }
     }
-    if (action == ACT_NONE) {
-      const double bound = g.u * maxm;
-      action = (fabs(amm) >= bound) ? ACT_1X1 : ACT_REJECT;
-    }
+    // after an elimination: the next candidate and the progress flag (a
+    // fallback step restarts the pass and does not count as progress)
+    const int next1 = fb ? nelim + 1 : m + 1;
+    const int next2 = fb ? nelim + 2 : m + 2;
+    const int prog = fb ? 0 : 1;
     // Every thread has read the values behind the decision before any
     // thread starts the interchanges and writes below: without this wait a
     // fast wave can swap rows that a slow wave is still reading, and the
@@ -386,7 +426,7 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) 
     __syncthreads();
 
     if (action == ACT_ZERO) {
-      sym_swap(g, m, nelim);
+      sym_swap(g, mc, nelim);
       const int k = nelim;
       for (int i = k + 1 + threadIdx.x; i < p; i += PIV_THREADS) CM(g.T, i, k, g.lda) = 0.0;
       for (int i = threadIdx.x; i < g.r; i += PIV_THREADS) CM(g.R, i, k, g.ldr) = 0.0;
@@ -397,13 +437,13 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) 
         pv_d[2 * k] = 0.0;
         pv_d[2 * k + 1] = 0.0;
         sh.nelim = nelim + 1;
-        sh.m = m + 1;
-        sh.progress = 1;
+        sh.m = next1;
+        sh.progress = prog;
         sh.status |= ST_ZERO_PIVOT;
       }
     } else if (action == ACT_2X2) {
       sym_swap(g, t, nelim);
-      sym_swap(g, m, nelim + 1);
+      sym_swap(g, mc, nelim + 1);
       const int k = nelim;
       const int s0 = sh.nslot;
       const double a11 = lazy_a(g, k, k), a21 = lazy_a(g, k + 1, k);
@@ -458,11 +498,11 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) 
         sh.sk[s0 + 1] = k + 1;
         sh.nslot = s0 + 2;
         sh.nelim = nelim + 2;
-        sh.m = m + 2;
-        sh.progress = 1;
+        sh.m = next2;
+        sh.progress = prog;
       }
     } else if (action == ACT_1X1) {
-      sym_swap(g, m, nelim);
+      sym_swap(g, mc, nelim);
       const int k = nelim;
       const int s0 = sh.nslot;
       const double dk = lazy_a(g, k, k);
@@ -490,8 +530,8 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) 
         sh.sk[s0] = k;
         sh.nslot = s0 + 1;
         sh.nelim = nelim + 1;
-        sh.m = m + 1;
-        sh.progress = 1;
+        sh.m = next1;
+        sh.progress = prog;
       }
     } else {
       __syncthreads();
@@ -527,33 +567,20 @@ __global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) 
   }
 }
 
+__global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) { pivot_decide_body(g); }
+
 // ---------------------------------------------------------------------------
 // apply: materialise the pending batch on the trailing square and on R
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void pivot_apply_kernel(PivotArgs g) {
-  __shared__ int kind[NSLOT], sk[NSLOT];
-  __shared__ int s_nslot, s_nelim;
-  const PivState* st = g.st;
-  if (threadIdx.x == 0) {
-    s_nslot = st->nslot;
-    s_nelim = st->nelim;
-  }
-  if (threadIdx.x < NSLOT) {
-    kind[threadIdx.x] = st->slot_kind[threadIdx.x];
-    sk[threadIdx.x] = st->slot_k[threadIdx.x];
-  }
-  __syncthreads();
-  const int nslot = s_nslot;
-  if (nslot == 0) return;
-  const int p = g.p, nelim = s_nelim;
+// One 64 x 64 tile b of the trailing square (tiles_a of them) or of R,
+// thread t of 256: 4 consecutive rows x 4 columns.
+CTP_DEV void pivot_apply_tile(const PivotArgs& g, int b, int t, int nslot, int nelim, const int* kind,
+                              const int* sk) {
+  const int p = g.p;
   const int nt = p - nelim;
-  if (nt <= 0) return;
   const int tw = (nt + APPLY_TILE - 1) / APPLY_TILE;
   const int tiles_a = tw * tw;
-  const int tiles_r = ((g.r + APPLY_TILE - 1) / APPLY_TILE) * tw;
-  const int b = blockIdx.x;
-  if (b >= tiles_a + tiles_r) return;
   bool in_r;
   int i0, j0;
   if (b < tiles_a) {
@@ -570,8 +597,8 @@ __global__ __launch_bounds__(256) void pivot_apply_kernel(PivotArgs g) {
   double* X = in_r ? g.R : g.T;
   const int ldx = in_r ? g.ldr : g.lda;
   // thread: 4 consecutive rows x 4 columns (16 threads cover 64 rows)
-  const int ib = i0 + (threadIdx.x % 16) * 4;
-  const int jb = j0 + (threadIdx.x / 16) * 4;
+  const int ib = i0 + (t % 16) * 4;
+  const int jb = j0 + (t / 16) * 4;
   double v[4][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
@@ -620,17 +647,189 @@ __global__ __launch_bounds__(256) void pivot_apply_kernel(PivotArgs g) {
     }
 }
 
+CTP_DEV int pivot_apply_tiles(const PivotArgs& g, int nelim) {
+  const int nt = g.p - nelim;
+  if (nt <= 0) return 0;
+  const int tw = (nt + APPLY_TILE - 1) / APPLY_TILE;
+  return tw * tw + ((g.r + APPLY_TILE - 1) / APPLY_TILE) * tw;
+}
+
+__global__ __launch_bounds__(256) void pivot_apply_kernel(PivotArgs g) {
+  __shared__ int kind[NSLOT], sk[NSLOT];
+  __shared__ int s_nslot, s_nelim;
+  const PivState* st = g.st;
+  if (threadIdx.x == 0) {
+    s_nslot = st->nslot;
+    s_nelim = st->nelim;
+  }
+  if (threadIdx.x < NSLOT) {
+    kind[threadIdx.x] = st->slot_kind[threadIdx.x];
+    sk[threadIdx.x] = st->slot_k[threadIdx.x];
+  }
+  __syncthreads();
+  const int nslot = s_nslot;
+  if (nslot == 0) return;
+  if ((int)blockIdx.x >= pivot_apply_tiles(g, s_nelim)) return;
+  pivot_apply_tile(g, blockIdx.x, threadIdx.x, nslot, s_nelim, kind, sk);
+}
+
+// ---------------------------------------------------------------------------
+// the whole search in one workgroup: decide, then the same workgroup
+// applies the batch (four tiles at a time) -- for trapezoids small enough
+// that one CU can sweep them, e.g. a compressed trapezoid with p <= 256.
+// Same arithmetic, in the same order, as the decide / apply launches.
+// ---------------------------------------------------------------------------
+
+__shared__ int pw_kind[NSLOT], pw_sk[NSLOT], pw_info[3];
+
+CTP_DEV void pivot_factor_wg_body(const PivotArgs& g) {
+  pivot_init_body(g, threadIdx.x, PIV_THREADS);
+  __syncthreads();
+  const int rounds = g.p / (NSLOT - 1) + 2;
+  for (int q = 0; q < rounds; ++q) {
+    pivot_decide_body(g);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      pw_info[0] = g.st->nslot;
+      pw_info[1] = g.st->nelim;
+      pw_info[2] = g.st->done;
+    }
+    if (threadIdx.x < NSLOT) {
+      pw_kind[threadIdx.x] = g.st->slot_kind[threadIdx.x];
+      pw_sk[threadIdx.x] = g.st->slot_k[threadIdx.x];
+    }
+    __syncthreads();
+    const int nslot = pw_info[0], nelim = pw_info[1], done = pw_info[2];
+    if (nslot > 0) {
+      const int tiles = pivot_apply_tiles(g, nelim);
+      for (int b = threadIdx.x / 256; b < tiles; b += PIV_THREADS / 256)
+        pivot_apply_tile(g, b, threadIdx.x % 256, nslot, nelim, pw_kind, pw_sk);
+    }
+    __syncthreads();
+    if (done || nslot == 0) break;
+  }
+}
+
+__global__ __launch_bounds__(PIV_THREADS) void pivot_factor_wg_kernel(PivotArgs g) { pivot_factor_wg_body(g); }
+
+// one workgroup per supernode of a batch
+__global__ __launch_bounds__(PIV_THREADS) void pivot_factor_batch_kernel(const PivotArgs* __restrict__ args,
+                                                                          int count) {
+  if ((int)blockIdx.x >= count) return;
+  const PivotArgs g = args[blockIdx.x];
+  pivot_factor_wg_body(g);
+}
+
+size_t pivot_lds_bytes(int p, int r);
+
+// ---------------------------------------------------------------------------
+// batches: per-node descriptors and pivot-search arguments built on the
+// device from the caller's ctp_node array
+// ---------------------------------------------------------------------------
+
+__global__ void batch_setup_kernel(const ctp_node* __restrict__ in, int count, int method, unsigned flags,
+                                   double u, double small, double* panels, double* s, int* perm, int* piv,
+                                   double* d, int* nelim, int* status, unsigned char* work,
+                                   BatchNode* __restrict__ nodes, PivotArgs* __restrict__ pargs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const ctp_node c = in[i];
+  const int r = c.n - c.p;
+  BatchNode nd;
+  nd.n = c.n;
+  nd.p = c.p;
+  nd.lda = c.lda;
+  nd.lds = c.lds;
+  nd.nchunks = relaxed_chunk_count(r);
+  const int nt = (r + 127) / 128;
+  nd.ntiles = (s && c.s_off >= 0) ? nt * (nt + 1) / 2 : 0;
+  nd.tile_off = c.tile_off;
+  nd.a = panels + c.a_off;
+  nd.s = (s && c.s_off >= 0) ? s + c.s_off : nullptr;
+  nd.perm = perm + c.out_off;
+  nd.piv = piv + c.out_off;
+  nd.d = d + 2 * c.out_off;
+  nd.nelim = nelim + i;
+  nd.status = status + i;
+  nd.work = work + c.work_off;
+  nodes[i] = nd;
+  status[i] = 0;
+  nelim[i] = 0;
+  const Workspace ws = workspace_layout(c.n, c.p, method);
+  PivotArgs g;
+  g.p = c.p;
+  g.T = nd.a;
+  g.lda = c.lda;
+  if (method == CTP_RESTRICTED) {
+    g.r = 0;
+    g.R = nullptr;
+    g.ldr = 1;
+    g.abs_update = 0;
+  } else {
+    g.r = c.p;
+    g.R = reinterpret_cast<double*>(nd.work + ws.c_off);
+    g.ldr = c.p;
+    g.abs_update = method == CTP_STRICT;
+  }
+  g.root = (flags & CTP_FLAG_ROOT) ? 1 : 0;
+  g.u = u;
+  g.small = small;
+  g.perm = nd.perm;
+  g.piv = nd.piv;
+  g.d = nd.d;
+  g.nelim_out = nd.nelim;
+  g.status = nd.status;
+  g.st = reinterpret_cast<PivState*>(nd.work + ws.st_off);
+  g.wbuf = reinterpret_cast<double*>(nd.work + ws.wb_off);
+  pargs[i] = g;
+}
+
+size_t batch_header_bytes(int count) {
+  return align_up((size_t)count * sizeof(BatchNode), 256) + align_up((size_t)count * sizeof(PivotArgs), 256) + 256;
+}
+
+int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags, double u, double small,
+                       double* panels, double* s, int* perm, int* piv, double* d, int* nelim, int* status,
+                       void* work, BatchNode** nodes_out, void** pargs_out, unsigned int** counter_out,
+                       hipStream_t stream) {
+  unsigned char* base = static_cast<unsigned char*>(work);
+  BatchNode* nodes = reinterpret_cast<BatchNode*>(base);
+  PivotArgs* pargs = reinterpret_cast<PivotArgs*>(base + align_up((size_t)count * sizeof(BatchNode), 256));
+  unsigned int* counter = reinterpret_cast<unsigned int*>(
+      base + align_up((size_t)count * sizeof(BatchNode), 256) + align_up((size_t)count * sizeof(PivotArgs), 256));
+  batch_setup_kernel<<<(count + 127) / 128, 128, 0, stream>>>(in, count, method, flags, u, small, panels, s, perm,
+                                                             piv, d, nelim, status, base, nodes, pargs);
+  *nodes_out = nodes;
+  *pargs_out = pargs;
+  *counter_out = counter;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipStream_t stream) {
+  const size_t lds = pivot_lds_bytes(max_p, max_r);
+  if (max_p > CTP_MAX_P || lds + 16 * 1024 > 160 * 1024) return -2;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)pivot_factor_batch_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  }
+  pivot_factor_batch_kernel<<<count, PIV_THREADS, lds, stream>>>(static_cast<const PivotArgs*>(pargs), count);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
 size_t pivot_lds_bytes(int p, int r) {
   const int rc = r < RCACHE ? r : RCACHE;
   return (size_t)NSLOT * p * sizeof(double) * 2 + (size_t)NSLOT * rc * sizeof(double);
 }
 
 int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, int abs_update,
-                        double u, double small, int* perm, int* piv, double* d, int* nelim,
-                        int* status, void* state, double* wbuf, hipStream_t stream) {
+                        int root, int one_wg, double u, double small, int* perm, int* piv, double* d,
+                        int* nelim, int* status, void* state, double* wbuf, hipStream_t stream) {
   PivotArgs g;
   g.p = p; g.T = a11; g.lda = lda; g.r = r; g.R = R; g.ldr = ldr;
-  g.abs_update = abs_update; g.u = u; g.small = small;
+  g.abs_update = abs_update; g.root = root; g.u = u; g.small = small;
   g.perm = perm; g.piv = piv; g.d = d; g.nelim_out = nelim; g.status = status;
   g.st = static_cast<PivState*>(state);
   g.wbuf = wbuf;
@@ -640,6 +839,16 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
     hipError_t e = hipFuncSetAttribute((const void*)pivot_decide_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  }
+  if (one_wg) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)pivot_factor_wg_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+    }
+    pivot_factor_wg_kernel<<<1, PIV_THREADS, lds, stream>>>(g);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
   }
   const size_t sq = (size_t)p * p;
   const unsigned init_blocks = (unsigned)std::min<size_t>((sq + 255) / 256 + 1, 2048);

@@ -16,6 +16,8 @@
 // the 64 tiles resident on one XCD share 8 row panels and 8 column panels
 // in its L2.  Tiles strictly above the diagonal exit at once.
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace ctp {
@@ -210,6 +212,7 @@ struct SchurWArgs {
   int lds;
   int ntm, ntn;
   int per_xcd;
+  int tiled;           // 1: s is this tile's own 128 x 128 block (ld 128)
 };
 
 // Main loop and epilogue of one tile.  VEC: every row of both operands
@@ -218,7 +221,9 @@ struct SchurWArgs {
 // VAR selects the schedule: bit 0 writes the next chunk into LDS after
 // three of the four k steps (so a chunk ends with the barrier alone), bit 1
 // pads the LDS rows by 8 doubles.  The default is both (VAR 3), the fastest
-// measured; a second register stage (loads two chunks ahead) spills.
+// measured; a second register stage (loads two chunks ahead) spills.  Bit 3
+// subtracts the product from the output instead of storing it (the trailing
+// update of a right-looking factorization).
 template <int VAR>
 struct SchurWShape {
   static constexpr int LW = (VAR & 2) ? SC_BM + 8 : SC_BM;   // LDS row stride (doubles)
@@ -364,7 +369,12 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wm * 64 + x * 16 + lk + 4 * q;
         const int j = j0 + wn * 64 + y * 16 + lrow;
-        if (i < iend && j <= i) g.s[(size_t)j * g.lds + (i - g.row0)] = acc[x][y][q];
+        if (i < iend && j <= i) {
+          double* dst = g.tiled ? g.s + (size_t)(j - j0) * SC_BM + (i - i0)
+                                : g.s + (size_t)j * g.lds + (i - g.row0);
+          if (VAR & 8) *dst -= acc[x][y][q];   // trailing update: C -= L21 W^T
+          else *dst = acc[x][y][q];
+        }
       }
 }
 
@@ -419,6 +429,7 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
   g.nrows = nrows;
   g.s = s;
   g.lds = lds;
+  g.tiled = 0;
   g.ntm = (nrows + SC_BM - 1) / SC_BM;
   g.ntn = (row0 + nrows + SC_BN - 1) / SC_BN;
   const int total = g.ntm * g.ntn;
@@ -434,6 +445,126 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
     case 2: rc = launch_schur_w_var<1>(g, vec, grid, stream); break;
     default: rc = launch_schur_w_var<3>(g, vec, grid, stream); break;
   }
+  if (rc) return rc;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+// ---------------------------------------------------------------------------
+// Batched Form: one persistent launch over every tile of every node.  Each
+// workgroup takes the next tile number from a counter in the workspace,
+// finds its node by binary search over the nodes' first tile numbers, and
+// runs the same tile routine as the single-node Form on that node's L21 and
+// stored W.  Every workgroup leaves once the counter passes the last tile.
+// Tiles of a node are numbered along the rows of its lower triangle of
+// 128 x 128 tiles: t = tm (tm + 1) / 2 + tn, tn <= tm.
+// ---------------------------------------------------------------------------
+
+template <int VAR>
+__global__ __launch_bounds__(SC_THREADS, 2) void schur_queue_kernel(const BatchNode* __restrict__ nodes, int count,
+                                                                   int method, long long total, int tiled,
+                                                                   unsigned int* __restrict__ counter) {
+  __shared__ long long s_t;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = (long long)atomicAdd(counter, 1u);
+    __syncthreads();
+    const long long t = s_t;
+    __syncthreads();
+    if (t >= total) break;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (nodes[mid].tile_off <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchNode& nd = nodes[lo];
+    const long long local = t - nd.tile_off;
+    int tm = (int)((sqrt(8.0 * (double)local + 1.0) - 1.0) * 0.5);
+    while ((long long)(tm + 1) * (tm + 2) / 2 <= local) ++tm;
+    while ((long long)tm * (tm + 1) / 2 > local) --tm;
+    const int tn = (int)(local - (long long)tm * (tm + 1) / 2);
+    const Workspace ws = workspace_layout(nd.n, nd.p, method);
+    SchurWArgs g;
+    g.r = nd.n - nd.p;
+    g.l21 = nd.a + nd.p;
+    g.lda = nd.lda;
+    g.w = reinterpret_cast<const double*>(nd.work + ws.w_off);
+    g.ldw = ws.ldw;
+    g.nelim_p = nd.nelim;
+    g.p = nd.p;
+    g.row0 = 0;
+    g.nrows = g.r;
+    g.tiled = tiled;
+    g.s = tiled ? nd.s + (size_t)local * SC_BM * SC_BN : nd.s;
+    g.lds = tiled ? SC_BM : nd.lds;
+    const int i0 = tm * SC_BM, j0 = tn * SC_BN;
+    const int K = min(max(*nd.nelim, 0), nd.p);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(g.l21) | reinterpret_cast<uintptr_t>(g.w)) % 16 == 0) &&
+                         g.lda % 2 == 0 && g.ldw % 2 == 0;
+    if (aligned && i0 + SC_BM <= g.r && j0 + SC_BN <= g.r) schur_w_tile<true, VAR>(g, i0, j0, K, sc_dyn);
+    else schur_w_tile<false, VAR>(g, i0, j0, K, sc_dyn);
+    __syncthreads();   // LDS is reused by the next tile
+  }
+}
+
+__global__ void queue_reset_kernel(unsigned int* counter) { *counter = 0u; }
+
+template <int VAR>
+static int launch_schur_queue_var(const BatchNode* nodes, int count, int method, long long total, int tiled,
+                                  unsigned int* counter, unsigned grid, hipStream_t stream) {
+  constexpr int bytes = SchurWShape<VAR>::LDS_BYTES;
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(schur_queue_kernel<VAR>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  }
+  schur_queue_kernel<VAR><<<grid, SC_THREADS, bytes, stream>>>(nodes, count, method, total, tiled, counter);
+  return 0;
+}
+
+int launch_schur_batch(int count, const BatchNode* nodes, int method, long long total, int tiled,
+                       unsigned int* counter, int variant, int workgroups, hipStream_t stream) {
+  if (count <= 0 || total <= 0) return 0;
+  queue_reset_kernel<<<1, 1, 0, stream>>>(counter);
+  const unsigned grid = (unsigned)std::min<long long>(total, workgroups > 0 ? workgroups : 512);
+  int rc;
+  switch (variant) {
+    case 1: rc = launch_schur_queue_var<0>(nodes, count, method, total, tiled, counter, grid, stream); break;
+    case 2: rc = launch_schur_queue_var<1>(nodes, count, method, total, tiled, counter, grid, stream); break;
+    default: rc = launch_schur_queue_var<3>(nodes, count, method, total, tiled, counter, grid, stream); break;
+  }
+  if (rc) return rc;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+// C(i, j) -= sum_k L21(i, k) W(j, k) for the lower triangle i >= j of the
+// order-(n-p) matrix C (column-major, ldc): the trailing update of a
+// right-looking factorization, rows of L21 = rows p..n-1 of the panel.
+int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, int ldw,
+                       const int* nelim, double* c, int ldc, hipStream_t stream) {
+  SchurWArgs g;
+  g.r = n - p;
+  g.l21 = a + p;
+  g.lda = lda;
+  g.w = w;
+  g.ldw = ldw;
+  g.nelim_p = nelim;
+  g.p = p;
+  g.row0 = 0;
+  g.nrows = g.r;
+  g.s = c;
+  g.lds = ldc;
+  g.tiled = 0;
+  g.ntm = (g.r + SC_BM - 1) / SC_BM;
+  g.ntn = g.ntm;
+  const int total = g.ntm * g.ntn;
+  if (total == 0 || p == 0) return 0;
+  g.per_xcd = (total + SC_NXCD - 1) / SC_NXCD;
+  const unsigned grid = g.per_xcd * SC_NXCD;
+  const bool vec = ((reinterpret_cast<uintptr_t>(a + p) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&
+                   lda % 2 == 0 && ldw % 2 == 0;
+  int rc = launch_schur_w_var<11>(g, vec, grid, stream);
   if (rc) return rc;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;

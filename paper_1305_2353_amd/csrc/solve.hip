@@ -29,15 +29,19 @@ typedef double d4s __attribute__((ext_vector_type(4)));
 constexpr int SOLVE_THREADS = 256;   // 4 waves, 16 rows each
 constexpr int SOLVE_ROWS = 64;
 
+CTP_DEV void solve_gather_body(int r, const double* __restrict__ a21, int lda, const int* __restrict__ perm,
+                               double* __restrict__ w, int ldw, int j, int chunk) {
+  const double* src = a21 + (size_t)perm[j] * lda;
+  double* dst = w + (size_t)j * ldw;
+  const int i0 = chunk * 4096;
+  const int i1 = min(r, i0 + 4096);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a21,
                                                          int lda, const int* __restrict__ perm,
                                                          double* __restrict__ w, int ldw) {
-  const int j = blockIdx.y;
-  const double* src = a21 + (size_t)perm[j] * lda;
-  double* dst = w + (size_t)j * ldw;
-  const int i0 = blockIdx.x * 4096;
-  const int i1 = min(r, i0 + 4096);
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
+  solve_gather_body(r, a21, lda, perm, w, ldw, blockIdx.y, blockIdx.x);
 }
 
 // 2x2 pivot inverse entries, scaled as in the pivot search.
@@ -50,11 +54,14 @@ CTP_DEV void inv2x2(double a11, double a21, double a22, double& i11, double& i21
   i22 = f * a11;
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
-    int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
-    const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw) {
-  __shared__ int piv_s[CTP_MAX_P + 32];
-  __shared__ double d_s[2 * CTP_MAX_P + 64];
+__shared__ int slv_piv[CTP_MAX_P + 32];
+__shared__ double slv_d[2 * CTP_MAX_P + 64];
+
+CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
+                             const double* __restrict__ d, const int* __restrict__ nelim_p,
+                             double* __restrict__ w, int ldw, int bx) {
+  int* piv_s = slv_piv;
+  double* d_s = slv_d;
   for (int k = threadIdx.x; k < p + 32; k += SOLVE_THREADS) {
     piv_s[k] = k < p ? piv[k] : PIV_DELAYED;
     d_s[2 * k] = k < p ? d[2 * k] : 0.0;
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
 
   const int nelim = min(max(*nelim_p, 0), p);
   const int lane = threadIdx.x & 63;
-  const int r0 = (blockIdx.x * SOLVE_THREADS + threadIdx.x) / 64 * 16;   // first row of this wave
+  const int r0 = (bx * SOLVE_THREADS + (int)threadIdx.x) / 64 * 16;   // first row of this wave
   if (r0 >= r) return;
   double* a21 = a + p;
   const int ga = lane >> 4;          // accumulator rows ga + 4q
@@ -176,6 +183,41 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
 #pragma unroll
     for (int q = 0; q < 4; ++q) carry[q] = acc[q];
   }
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
+    int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
+    const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw) {
+  solve_mfma_body(r, p, a, lda, piv, d, nelim_p, w, ldw, blockIdx.x);
+}
+
+// Batched: the node is blockIdx.z (gather) / blockIdx.y (solve).
+__global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
+  const BatchNode& nd = nodes[blockIdx.z];
+  const int r = nd.n - nd.p;
+  if ((int)blockIdx.y >= nd.p || (int)blockIdx.x * 4096 >= r) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, method);
+  solve_gather_body(r, nd.a + nd.p, nd.lda, nd.perm, reinterpret_cast<double*>(nd.work + ws.w_off), ws.ldw,
+                    blockIdx.y, blockIdx.x);
+}
+
+__global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_batch_kernel(const BatchNode* __restrict__ nodes,
+                                                                         int method) {
+  const BatchNode& nd = nodes[blockIdx.y];
+  const int r = nd.n - nd.p;
+  if ((int)blockIdx.x * SOLVE_ROWS >= r) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, method);
+  solve_mfma_body(r, nd.p, nd.a, nd.lda, nd.piv, nd.d, nd.nelim, reinterpret_cast<double*>(nd.work + ws.w_off),
+                  ws.ldw, blockIdx.x);
+}
+
+int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream) {
+  if (count <= 0 || max_r <= 0 || max_p <= 0) return 0;
+  solve_gather_batch_kernel<<<dim3((max_r + 4095) / 4096, max_p, count), 256, 0, stream>>>(nodes, method);
+  solve_mfma_batch_kernel<<<dim3((max_r + SOLVE_ROWS - 1) / SOLVE_ROWS, count), SOLVE_THREADS, 0, stream>>>(nodes,
+                                                                                                        method);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
 
 // W = L21 D for the eliminated columns, from L21 and D (used after the

@@ -23,16 +23,37 @@ METHOD_IDS = {"tpp": CTP_TPP, "strict": CTP_STRICT, "relaxed": CTP_RELAXED,
               "restricted": CTP_RESTRICTED}
 CTP_PIV_ZERO, CTP_PIV_1X1, CTP_PIV_2X2_FIRST, CTP_PIV_2X2_SECOND, CTP_PIV_DELAYED = 0, 1, 2, -2, -1
 CTP_STATUS_ZERO_PIVOT, CTP_STATUS_NONFINITE, CTP_STATUS_RELAXED_RESCAN = 1, 2, 4
+CTP_STATUS_ROOT_FALLBACK = 8
+CTP_FLAG_ROOT = 1
+CTP_FLAG_ONE_WG = 2
+CTP_FLAG_S_TILED = 4
+SC_TILE = 128
+CTP_ERR_PANEL_TOO_WIDE = -900
+PREC_IDS = {"fp64": 0, "fp32": 1, "bf16": 2}
 CTP_MAX_P = 512
 
 # Every symbol declared in include/ctp.h.
 EXPORTED = ("ctp_default_opts", "ctp_version", "ctp_workspace_size", "ctp_compress",
-            "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode", "ctp_schur")
+            "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode", "ctp_schur",
+            "ctp_dense_workspace_size", "ctp_ldlt_dense", "ctp_ldlt_solve", "ctp_ldlt_refine",
+            "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched")
 
 
 class CtpOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("u", ctypes.c_double), ("small", ctypes.c_double),
                 ("prec", ctypes.c_int), ("tile", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class CtpNode(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("lda", ctypes.c_int), ("lds", ctypes.c_int),
+                ("a_off", ctypes.c_longlong), ("s_off", ctypes.c_longlong), ("out_off", ctypes.c_longlong),
+                ("work_off", ctypes.c_longlong), ("tile_off", ctypes.c_longlong)]
+
+
+class CtpBatchInfo(ctypes.Structure):
+    _fields_ = [("work_bytes", ctypes.c_size_t), ("tiles", ctypes.c_longlong), ("count", ctypes.c_int),
+                ("max_p", ctypes.c_int), ("max_r", ctypes.c_int), ("max_chunks", ctypes.c_int),
+                ("form_workgroups", ctypes.c_int)]
 
 
 class CtpError(RuntimeError):
@@ -61,6 +82,14 @@ def load(path=LIB_PATH):
         "ctp_solve_supernode": (I, [I, I, P, I, P, P, P, P, OPT, P, SZ, P]),
         "ctp_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
         "ctp_schur": (I, [I, I, P, I, P, P, P, I, I, P, I, OPT, P, SZ, P]),
+        "ctp_dense_workspace_size": (I, [I, I, OPT, I, ctypes.POINTER(SZ)]),
+        "ctp_ldlt_dense": (I, [I, I, P, I, OPT, P, P, P, P, ctypes.POINTER(I), P, SZ, P]),
+        "ctp_ldlt_solve": (I, [I, I, P, I, P, P, P, P, I, OPT, I, P, SZ, P]),
+        "ctp_ldlt_refine": (I, [I, I, P, I, P, I, P, P, P, P, I, P, I, OPT, I, D, I,
+                                ctypes.POINTER(I), ctypes.POINTER(D), P, SZ, P]),
+        "ctp_ldlt_adjoint": (I, [I, I, P, I, P, P, P, P, I, P, I, P, I, OPT, I, P, SZ, P]),
+        "ctp_batch_plan": (I, [I, P, OPT, ctypes.POINTER(CtpBatchInfo)]),
+        "ctp_supernode_batched": (I, [I, P, ctypes.POINTER(CtpBatchInfo), P, P, P, P, P, P, P, OPT, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -103,12 +132,14 @@ def device_panel(A, lda=None, device="cuda"):
     return buf.t()[:n, :] if lda != n else buf.t()
 
 
-def ctp_default_opts(method="relaxed", u=0.01, small=1e-20):
+def ctp_default_opts(method="relaxed", u=0.01, small=1e-20, prec="fp64", flags=0):
     o = CtpOpts()
     load().ctp_default_opts(ctypes.byref(o))
     o.method = METHOD_IDS[method] if isinstance(method, str) else int(method)
     o.u = u
     o.small = small
+    o.prec = PREC_IDS[prec] if isinstance(prec, str) else int(prec)
+    o.flags = flags
     return o
 
 
@@ -195,3 +226,180 @@ def ctp_schur(a, f, row0, nrows, opts, s=None, work=None):
     _check(load().ctp_schur(n, p, _ptr(a), lda, _ptr(f["piv"]), _ptr(f["d"]), _ptr(f["nelim"]), row0, nrows,
                             _ptr(s), lds, ctypes.byref(opts), _ptr(work), lwork, _stream()), "ctp_schur")
     return s
+
+
+# ---------------------------------------------------------------------------
+# dense LDL^T by supernode panels
+# ---------------------------------------------------------------------------
+
+def ctp_dense_workspace_size(N, pw, opts, nrhs_max=16):
+    out = ctypes.c_size_t(0)
+    _check(load().ctp_dense_workspace_size(N, pw, ctypes.byref(opts), nrhs_max, ctypes.byref(out)),
+           "ctp_dense_workspace_size")
+    return out.value
+
+
+def dense_workspace(N, pw, opts, nrhs_max=16, device="cuda"):
+    return torch.empty(max(ctp_dense_workspace_size(N, pw, opts, nrhs_max), 1), dtype=torch.uint8,
+                       device=device)
+
+
+def _square_args(a):
+    n, m, lda = _panel_args(a)
+    if n != m:
+        raise CtpError("square matrix expected")
+    return n, lda
+
+
+def ctp_ldlt_dense(a, pw, opts, work):
+    """P A P^T = L D L^T in place on the column-major N x N tensor a (lower
+    triangle read).  Returns perm, piv, d, status (device) and npanels."""
+    N, lda = _square_args(a)
+    perm = torch.empty(max(N, 1), dtype=torch.int32, device=a.device)
+    piv = torch.empty(max(N, 1), dtype=torch.int32, device=a.device)
+    d = torch.zeros(max(2 * N, 1), dtype=torch.float64, device=a.device)
+    status = torch.zeros(1, dtype=torch.int32, device=a.device)
+    npan = ctypes.c_int(0)
+    _check(load().ctp_ldlt_dense(N, pw, _ptr(a), lda, ctypes.byref(opts), _ptr(perm), _ptr(piv), _ptr(d),
+                                 _ptr(status), ctypes.byref(npan), _ptr(work), work.numel(), _stream()),
+           "ctp_ldlt_dense")
+    return {"perm": perm[:N], "piv": piv[:N], "d": d[:2 * N], "status": status, "npanels": npan.value,
+            "pw": pw}
+
+
+def ctp_ldlt_solve(a, f, b, opts, work):
+    """b <- A^-1 b in place (b: column-major N x nrhs float64 CUDA tensor)."""
+    N, lda = _square_args(a)
+    nb, nrhs, ldb = _panel_args(b)
+    assert nb == N
+    _check(load().ctp_ldlt_solve(N, nrhs, _ptr(a), lda, _ptr(f["perm"]), _ptr(f["piv"]), _ptr(f["d"]), _ptr(b),
+                                 ldb, ctypes.byref(opts), f["pw"], _ptr(work), work.numel(), _stream()),
+           "ctp_ldlt_solve")
+    return b
+
+
+def ctp_ldlt_refine(a0, a, f, b, opts, work, tol=1e-14, max_steps=10, x=None):
+    """FP64 iterative refinement; a0 holds the original matrix (both
+    triangles).  Returns (x, steps, backward-error history)."""
+    N, lda = _square_args(a)
+    _, lda0 = _square_args(a0)
+    nb, nrhs, ldb = _panel_args(b)
+    if x is None:
+        x = device_panel(torch.zeros(N, nrhs, dtype=torch.float64), device=a.device)
+    _, _, ldx = _panel_args(x)
+    steps = ctypes.c_int(0)
+    hist = (ctypes.c_double * (max_steps + 1))()
+    _check(load().ctp_ldlt_refine(N, nrhs, _ptr(a0), lda0, _ptr(a), lda, _ptr(f["perm"]), _ptr(f["piv"]),
+                                  _ptr(f["d"]), _ptr(b), ldb, _ptr(x), ldx, ctypes.byref(opts), f["pw"], tol,
+                                  max_steps, ctypes.byref(steps), hist, _ptr(work), work.numel(), _stream()),
+           "ctp_ldlt_refine")
+    return x, steps.value, list(hist)[:steps.value + 1]
+
+
+def ctp_ldlt_adjoint(a, f, x, xbar, opts, work, abar=None):
+    """bbar = A^-1 xbar (in place of xbar) and Abar = -sym(bbar x^T) (full
+    N x N, column-major), from the factors of ctp_ldlt_dense."""
+    N, lda = _square_args(a)
+    _, nrhs, ldx = _panel_args(x)
+    _, _, ldxb = _panel_args(xbar)
+    if abar is None:
+        abar = torch.empty((N, N), dtype=torch.float64, device=a.device).t()
+    _, ldg = _square_args(abar)
+    _check(load().ctp_ldlt_adjoint(N, nrhs, _ptr(a), lda, _ptr(f["perm"]), _ptr(f["piv"]), _ptr(f["d"]), _ptr(x),
+                                   ldx, _ptr(xbar), ldxb, _ptr(abar), ldg, ctypes.byref(opts), f["pw"], _ptr(work),
+                                   work.numel(), _stream()), "ctp_ldlt_adjoint")
+    return xbar, abar
+
+
+# ---------------------------------------------------------------------------
+# batches of supernodes
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """A batch of supernodes laid out in one panel buffer (each panel
+    column-major with lda = n), one S buffer (lds = n - p) and concatenated
+    outputs, planned once; run() enqueues ctp_supernode_batched.
+
+    shapes: list of (n, p).  form: which nodes get S (bool or list).
+    tiled: store each S as its lower 128 x 128 tiles (CTP_FLAG_S_TILED)."""
+
+    def __init__(self, shapes, opts, form=True, device="cuda", tiled=False):
+        self.shapes = [(int(n), int(p)) for n, p in shapes]
+        self.tiled = tiled
+        if tiled:
+            opts.flags |= CTP_FLAG_S_TILED
+        self.opts = opts
+        count = len(self.shapes)
+        forms = [bool(form)] * count if isinstance(form, bool) else [bool(f) for f in form]
+        nodes = (CtpNode * count)()
+        a_off = s_off = out_off = 0
+        for i, (n, p) in enumerate(self.shapes):
+            r = n - p
+            nd = nodes[i]
+            nd.n, nd.p, nd.lda, nd.lds = n, p, n, max(r, 1)
+            nd.a_off, nd.out_off = a_off, out_off
+            nd.s_off = s_off if forms[i] else -1
+            a_off += n * p
+            out_off += p
+            if forms[i]:
+                if tiled:
+                    nt = (r + SC_TILE - 1) // SC_TILE
+                    s_off += nt * (nt + 1) // 2 * SC_TILE * SC_TILE
+                else:
+                    s_off += max(r, 1) * r
+        self.info = CtpBatchInfo()
+        _check(load().ctp_batch_plan(count, ctypes.cast(nodes, ctypes.c_void_p), ctypes.byref(opts),
+                                     ctypes.byref(self.info)), "ctp_batch_plan")
+        self.nodes_host = nodes
+        raw = bytes(memoryview(nodes).cast("B"))
+        self.nodes = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        self.count = count
+        self.panels = torch.empty(max(a_off, 1), dtype=torch.float64, device=device)
+        self.S = torch.empty(max(s_off, 1), dtype=torch.float64, device=device) if s_off else None
+        self.perm = torch.empty(max(out_off, 1), dtype=torch.int32, device=device)
+        self.piv = torch.empty(max(out_off, 1), dtype=torch.int32, device=device)
+        self.d = torch.empty(max(2 * out_off, 1), dtype=torch.float64, device=device)
+        self.nelim = torch.zeros(max(count, 1), dtype=torch.int32, device=device)
+        self.status = torch.zeros(max(count, 1), dtype=torch.int32, device=device)
+        self.work = torch.empty(max(self.info.work_bytes, 1), dtype=torch.uint8, device=device)
+
+    def node(self, i):
+        return self.nodes_host[i]
+
+    def panel_view(self, i):
+        nd = self.nodes_host[i]
+        return self.panels[nd.a_off:nd.a_off + nd.n * nd.p].view(nd.p, nd.n).t()
+
+    def s_view(self, i):
+        """S of node i as an (r x r) tensor (tiled storage is assembled into
+        a dense lower triangle; entries above the diagonal are zero there)."""
+        nd = self.nodes_host[i]
+        r = nd.n - nd.p
+        if nd.s_off < 0 or self.S is None:
+            return None
+        if not self.tiled:
+            return self.S[nd.s_off:nd.s_off + nd.lds * r].view(r, nd.lds).t()[:r]
+        T = SC_TILE
+        nt = (r + T - 1) // T
+        out = torch.zeros((r, r), dtype=torch.float64, device=self.S.device)
+        t = 0
+        for tm in range(nt):
+            for tn in range(tm + 1):
+                blk = self.S[nd.s_off + t * T * T:nd.s_off + (t + 1) * T * T].view(T, T).t()
+                i1, j1 = min(r, (tm + 1) * T), min(r, (tn + 1) * T)
+                out[tm * T:i1, tn * T:j1] = blk[:i1 - tm * T, :j1 - tn * T]
+                t += 1
+        return torch.tril(out)
+
+    def outputs(self, i):
+        nd = self.nodes_host[i]
+        o = nd.out_off
+        return {"perm": self.perm[o:o + nd.p], "piv": self.piv[o:o + nd.p], "d": self.d[2 * o:2 * o + 2 * nd.p],
+                "nelim": self.nelim[i:i + 1], "status": self.status[i:i + 1]}
+
+    def run(self):
+        _check(load().ctp_supernode_batched(self.count, _ptr(self.nodes), ctypes.byref(self.info), _ptr(self.panels),
+                                            _ptr(self.S), _ptr(self.perm), _ptr(self.piv), _ptr(self.d),
+                                            _ptr(self.nelim), _ptr(self.status), ctypes.byref(self.opts),
+                                            _ptr(self.work), self.work.numel(), _stream()),
+               "ctp_supernode_batched")

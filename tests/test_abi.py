@@ -73,3 +73,24 @@ def test_workspace_size_and_argument_checks(lib):
     assert lib.ctp_solve_supernode(600, 50, fake, 600, fake, fake, fake, fake, ctypes.byref(o), fake,
                                    16, nul) == -11
     assert lib.ctp_compress(20, 10, fake, 20, 0, fake, 10, fake, fake, fake, 1 << 20, nul) == -5
+    # dense driver: host-side argument checks
+    dsz = ctypes.c_size_t(0)
+    assert lib.ctp_dense_workspace_size(100, 0, ctypes.byref(o), 4, ctypes.byref(dsz)) == -2
+    assert lib.ctp_dense_workspace_size(100, 513, ctypes.byref(o), 4, ctypes.byref(dsz)) == -2
+    assert lib.ctp_dense_workspace_size(100, 32, ctypes.byref(o), 17, ctypes.byref(dsz)) == -4
+    assert lib.ctp_dense_workspace_size(100, 32, ctypes.byref(o), 4, ctypes.byref(dsz)) == 0
+    small = dsz.value
+    lowp = ctp.ctp_default_opts("relaxed", prec="fp32")
+    assert lib.ctp_dense_workspace_size(100, 32, ctypes.byref(lowp), 4, ctypes.byref(dsz)) == 0
+    assert dsz.value > small          # the FP32 trailing matrix and operand rows
+    bad_prec = ctp.ctp_default_opts("relaxed", prec=3)
+    assert lib.ctp_dense_workspace_size(100, 32, ctypes.byref(bad_prec), 4, ctypes.byref(dsz)) == -3
+    np_ = ctypes.c_int(0)
+    assert lib.ctp_ldlt_dense(100, 32, fake, 99, ctypes.byref(o), fake, fake, fake, fake, ctypes.byref(np_),
+                              fake, 1 << 30, nul) == -4
+    assert lib.ctp_ldlt_dense(100, 32, fake, 100, ctypes.byref(o), fake, fake, fake, fake, ctypes.byref(np_),
+                              fake, 16, nul) == -12
+    assert lib.ctp_ldlt_solve(100, 17, fake, 100, fake, fake, fake, fake, 100, ctypes.byref(o), 32, fake,
+                              1 << 30, nul) == -2
+    assert lib.ctp_ldlt_solve(100, 2, fake, 100, fake, fake, fake, fake, 100, ctypes.byref(o), 32, fake,
+                              16, nul) == -13

@@ -177,3 +177,25 @@ def test_schur_stored_w_ragged(shape):
     S_ref = schur_rows(ref, rows)
     for q, i in enumerate(rows):
         assert rel_err(s[i, :i + 1], S_ref[q, :i + 1]) <= FP64_TOL, (shape, i)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("shape", [(256, 32), (3000, 256), (1200, 97)])
+def test_one_workgroup_factor_matches_oracle(method, shape):
+    """CTP_FLAG_ONE_WG: the whole pivot search in one workgroup gives the
+    oracle's decisions and values bit for bit, like the multi-launch path."""
+    from paper_1305_2353_amd import ctp
+    n, p = shape
+    A = supernode(n, p, seed=3 * n + p, n_small=min(4, p))
+    _announce("one-wg factor", method, shape)
+    ref = factor_supernode(A, p, method)
+    if ref.trap.fragile_steps():
+        pytest.skip("near-tie decision in this draw")
+    a = ctp.device_panel(A)
+    opts = ctp.ctp_default_opts(method, flags=ctp.CTP_FLAG_ONE_WG)
+    work = ctp.workspace(n, p, opts)
+    f = ctp.ctp_supernode(a, opts, work=work)
+    torch.cuda.synchronize()
+    g = {"out": a.cpu().numpy(), "perm": f["perm"].cpu().numpy(), "piv": f["piv"].cpu().numpy(),
+         "d": f["d"].cpu().numpy(), "nelim": int(f["nelim"].item())}
+    assert_parity(g, ref, p, method, check_s=False)

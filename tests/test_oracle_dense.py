@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle.dense import (backward_error, ldlt_dense, ldlt_solve, reconstruct, refine,
-                          solve_d)
+                          solve_adjoint, solve_d)
 from oracle.threshold import factor_trapezoid
 from workloads import dense_indefinite, supernode
 
@@ -134,3 +134,25 @@ def test_panel_widths_without_delays():
     A[np.arange(600), np.arange(600)] = 1.0
     F = ldlt_dense(A, 256, "relaxed")
     assert [w for _, w, _ in F.panels] == [256, 256, 88]
+
+
+def test_adjoint_matches_central_differences():
+    """<Abar, E> against central differences of L(A) = sum w * A^-1 b along
+    symmetric directions E, and Bbar against differences in b."""
+    A, lam, B = dense_indefinite(24, seed=8, lam_lo=0.1, nrhs=2)
+    rng = np.random.default_rng(3)
+    W = rng.standard_normal(B.shape)
+    loss = lambda M, R: float((W * np.linalg.solve(M, R)).sum())
+    X = np.linalg.solve(A, B)
+    Bbar, Abar = solve_adjoint(A, X, W)
+    assert np.allclose(Abar, Abar.T, rtol=0, atol=1e-15)
+    h = 1e-6
+    for _ in range(4):
+        Z = rng.standard_normal(A.shape)
+        E = (Z + Z.T) / 2
+        E /= np.linalg.norm(E)
+        fd = (loss(A + h * E, B) - loss(A - h * E, B)) / (2 * h)
+        assert fd == pytest.approx(float((Abar * E).sum()), rel=1e-6, abs=1e-8)
+        Eb = rng.standard_normal(B.shape)
+        fdb = (loss(A, B + h * Eb) - loss(A, B - h * Eb)) / (2 * h)
+        assert fdb == pytest.approx(float((Bbar * Eb).sum()), rel=1e-6, abs=1e-8)

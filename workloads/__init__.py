@@ -16,6 +16,9 @@ construction.  The recipes here are:
 * dense_indefinite(N): Q diag(lam) Q^T with Q the orthogonal factor of a
   Gaussian matrix (Householder QR, signs fixed by diag(R)) and lam half
   negative, half positive, |lam| ~ U[lo, 1], shuffled.
+  dense_indefinite_torch(N) draws the same recipe with torch on a device
+  (its own seeded stream, so a different matrix of the same law): the
+  N = 16384 case would take minutes of CPU QR.
 * batch of supernodes: n log-uniform, p uniform with p <= n/4.
 
 Every array is float64, row index first (n x p); the binding stores panels
@@ -90,3 +93,41 @@ def batch_panel(n, p, rng, small_prob=0.01, small_scale=1e-8):
     A11[mask, mask] *= small_scale
     A21 = rng.standard_normal((n - p, p))
     return np.vstack([A11, A21])
+
+
+def dense_indefinite_torch(N, seed=0, lam_lo=1e-3, nrhs=0, device="cuda"):
+    """dense_indefinite's recipe drawn with torch on `device` (FP64).
+
+    Returns (A, lam, B) as device tensors (B None when nrhs == 0); A is
+    row-major N x N and symmetric, so it is its own column-major copy."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Z = torch.randn((N, N), dtype=torch.float64, device=device, generator=g)
+    Q, R = torch.linalg.qr(Z)
+    del Z
+    Q = Q * torch.sign(torch.diagonal(R))
+    del R
+    half = N // 2
+    u = torch.rand(N, dtype=torch.float64, device=device, generator=g) * (1.0 - lam_lo) + lam_lo
+    lam = torch.cat([-u[:half], u[half:]])
+    lam = lam[torch.randperm(N, device=device, generator=g)]
+    A = (Q * lam) @ Q.T
+    del Q
+    A = 0.5 * (A + A.T)
+    B = torch.randn((N, nrhs), dtype=torch.float64, device=device, generator=g) if nrhs else None
+    return A, lam, B
+
+
+def batch_panel_torch(n, p, gen, device="cuda", small_prob=0.01, small_scale=1e-8):
+    """batch_panel's recipe drawn with torch on `device` from generator
+    `gen` (FP64, n x p, row index first)."""
+    import torch
+    G = torch.randn((p, p), dtype=torch.float64, device=device, generator=gen)
+    A11 = torch.tril(G) + torch.tril(G, -1).T
+    mask = torch.rand(p, dtype=torch.float64, device=device, generator=gen) < small_prob
+    a = torch.diagonal(A11).clone()
+    d = torch.where(mask, a * small_scale, a)
+    A11 = A11 - torch.diag(a) + torch.diag(d)
+    A21 = torch.randn((n - p, p), dtype=torch.float64, device=device, generator=gen)
+    return torch.cat([A11, A21])
