@@ -92,14 +92,17 @@ def cpu_baseline(A, p, method, blocks):
                       f"4096-row blocks {list(blocks)} of {-(-r // BLOCK_ROWS)}"}
 
 
-def dense_section(N, pw=256, method="relaxed", seed=0, nrhs=8, tol=1e-14):
+def dense_section(N, pw=256, method="relaxed", seed=0, nrhs=8, tol=1e-14, u=0.5):
     """Dense symmetric indefinite system of order N (Q diag(lam) Q^T, half of
     lam negative, |lam| in [1e-3, 1]) factorized right-looking in panels of
     pw columns with compressed pivoting, then solved for nrhs right-hand
     sides with FP64 refinement to a backward error <= tol.  Run with the
     trailing update in FP64, FP32 and BF16 (FP32 accumulation).  Times are
     wall clock around each call on a resident matrix (the factorization
-    reads nelim back after every panel)."""
+    reads nelim back after every panel).  Threshold u = 0.5: refinement from
+    reduced-precision factors converges when kappa * unit roundoff * growth
+    < 1, and growth at u = 0.01 is ~25x larger than at u = 0.5 on this
+    construction."""
     import torch
     from paper_1305_2353_amd import ctp
     from workloads import dense_indefinite_torch
@@ -108,10 +111,10 @@ def dense_section(N, pw=256, method="relaxed", seed=0, nrhs=8, tol=1e-14):
     b = B.t().contiguous().t()          # column-major N x nrhs
     torch.cuda.synchronize()
     flops = N ** 3 / 3.0
-    res = {"workload": f"dense N={N} Q diag(lam) Q^T, |lam| in [1e-3,1], {nrhs} RHS, panels of {pw}, {method}",
+    res = {"workload": f"dense N={N} Q diag(lam) Q^T, |lam| in [1e-3,1], {nrhs} RHS, panels of {pw}, {method}, u={u}",
            "flop_factor": flops}
     for prec, steps_max in (("fp64", 10), ("fp32", 10), ("bf16", 30)):
-        opts = ctp.ctp_default_opts(method, prec=prec)
+        opts = ctp.ctp_default_opts(method, u=u, prec=prec)
         work = ctp.dense_workspace(N, pw, opts, nrhs)
         best = None
         for rep in range(2):

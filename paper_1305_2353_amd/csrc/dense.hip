@@ -358,6 +358,8 @@ __global__ void dense_axpy_kernel(double* __restrict__ x, int ldx, const double*
 // factors), Abar = -sum_c (bbar_c x_c^T + x_c bbar_c^T) / 2, full N x N
 // ---------------------------------------------------------------------------
 
+// Entry (i, j), i >= j, is computed once and written to (i, j) and (j, i),
+// so Abar is exactly symmetric whatever the compiler contracts.
 __global__ __launch_bounds__(256) void dense_sym_outer_kernel(const double* __restrict__ bbar, int ldb,
                                                               const double* __restrict__ x, int ldx, int N,
                                                               int nrhs, double* __restrict__ abar, int ldg) {
@@ -368,17 +370,13 @@ __global__ __launch_bounds__(256) void dense_sym_outer_kernel(const double* __re
     xj[threadIdx.x] = x[(size_t)threadIdx.x * ldx + j];
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = j + blockIdx.x * 256 + threadIdx.x;
   if (i >= N) return;
-  // both products rounded before the sum, so that entries (i, j) and
-  // (j, i) are the same two numbers added (Abar exactly symmetric)
   double s = 0.0;
-  for (int c = 0; c < nrhs; ++c) {
-    const double t1 = __dmul_rn(bbar[(size_t)c * ldb + i], xj[c]);
-    const double t2 = __dmul_rn(x[(size_t)c * ldx + i], bj[c]);
-    s = __dadd_rn(s, __dadd_rn(t1, t2));
-  }
-  abar[(size_t)j * ldg + i] = -0.5 * s;
+  for (int c = 0; c < nrhs; ++c) s += bbar[(size_t)c * ldb + i] * xj[c] + x[(size_t)c * ldx + i] * bj[c];
+  const double v = -0.5 * s;
+  abar[(size_t)j * ldg + i] = v;
+  abar[(size_t)i * ldg + j] = v;
 }
 
 // ---------------------------------------------------------------------------
