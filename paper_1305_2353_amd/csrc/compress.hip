@@ -122,6 +122,8 @@ struct Cand {
   int i;      // row of A21
 };
 
+static size_t relaxed_flag_bytes(int r) { return (size_t)((r > 0 ? r : 1) + 31) / 32 * sizeof(unsigned); }
+
 CTP_DEV bool better(double v1, int i1, double v2, int i2) {
   return v1 > v2 || (v1 == v2 && i1 < i2);
 }
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(256) void relaxed_topk_kernel(int r, int p, const d
 }
 
 // One workgroup of 1024 threads.  Dynamic LDS: final candidate lists
-// (p * K Cand) + chosen rows (p ints).
+// (p * K Cand) + chosen rows (p ints) + a bitmap of chosen rows (r bits).
 extern __shared__ unsigned char cmp_smem[];
 
 CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, int lda, int nchunks,
@@ -214,8 +216,10 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
   constexpr int K = RELAXED_TOPK;
   Cand* lists = reinterpret_cast<Cand*>(cmp_smem);
   int* chosen = reinterpret_cast<int*>(lists + (size_t)p * K);
+  unsigned* flags = reinterpret_cast<unsigned*>(chosen + p);   // one bit per A21 row
   __shared__ int s_pick;
   __shared__ int s_need_scan;
+  __shared__ int s_taken;
   __shared__ double red_v[16];
   __shared__ int red_i[16];
 
@@ -252,69 +256,84 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
   }
   __syncthreads();
 
-  // 2. Column order with flagging.  Wave 0 tests candidates against the
-  //    rows already chosen; a column whose K candidates are all taken is
-  //    rescanned by the whole workgroup.
+  // 2. Column order with flagging.  A bitmap of the rows already chosen
+  //    sits in LDS; wave 0 walks the columns on its own (lane q tests
+  //    candidate q, the first free one wins), and the whole workgroup joins
+  //    only to rescan a column whose K candidates are all taken.
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
-  int taken = 0;                       // rows chosen so far (== j unless rows ran out)
-  for (int j = 0; j < p; ++j) {
-    if (threadIdx.x == 0) { s_pick = -1; s_need_scan = 0; }
-    __syncthreads();
-    if (taken >= r) {
-      if (threadIdx.x == 0) chosen[j] = -1;
-      __syncthreads();
-      continue;
-    }
+  const int nwords = (r + 31) / 32;
+  for (int q = threadIdx.x; q < nwords; q += blockDim.x) flags[q] = 0u;
+  if (threadIdx.x == 0) s_taken = 0;
+  __syncthreads();
+  int j = 0;
+  while (j < p) {
     if (wave == 0) {
-      int pick = -1;
-      for (int q = 0; q < K && pick < 0; ++q) {
-        int cand_row = lists[(size_t)j * K + q].i;
-        if (cand_row < 0) break;
-        bool hit = false;
-        for (int s = lane; s < j; s += 64) hit = hit || (chosen[s] == cand_row);
-        unsigned long long any = __ballot(hit);
-        if (!any) pick = cand_row;
+      int taken = s_taken;
+      int jj = j;
+      int need = 0;
+      for (; jj < p; ++jj) {
+        if (taken >= r) {
+          if (lane == 0) chosen[jj] = -1;
+          continue;
+        }
+        const int row = lane < K ? lists[(size_t)jj * K + lane].i : -1;
+        const bool free_row = row >= 0 && !((flags[row >> 5] >> (row & 31)) & 1u);
+        const unsigned long long m = __ballot(free_row);
+        if (m == 0ull) {
+          need = 1;
+          break;
+        }
+        const int q = __ffsll((long long)m) - 1;
+        const int pick = __shfl(row, q, 64);
+        if (lane == 0) {
+          chosen[jj] = pick;
+          flags[pick >> 5] |= 1u << (pick & 31);
+        }
+        ++taken;
       }
       if (lane == 0) {
-        if (pick >= 0) s_pick = pick;
-        else s_need_scan = 1;
+        s_pick = jj;          // first column not finished
+        s_need_scan = need;
+        s_taken = taken;
       }
     }
     __syncthreads();
-    if (s_need_scan) {
-      // Full rescan of column j over rows not yet chosen.
-      const double* colp = a21 + (size_t)j * lda;
-      double bv = -1.0;
-      int bi = 0x7fffffff;
-      for (int i = threadIdx.x; i < r; i += blockDim.x) {
-        double v = fabs(colp[i]);
-        if (!better(v, i, bv, bi)) continue;
-        bool hit = false;
-        for (int s = 0; s < j; ++s) hit = hit || (chosen[s] == i);
-        if (!hit) { bv = v; bi = i; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ov = __shfl_xor(bv, off, 64);
-        int oi = __shfl_xor(bi, off, 64);
-        if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
-      }
-      if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double xv = red_v[0];
-        int xi = red_i[0];
-        for (int w = 1; w < nwaves; ++w)
-          if (better(red_v[w], red_i[w], xv, xi)) { xv = red_v[w]; xi = red_i[w]; }
-        s_pick = (xv >= 0.0) ? xi : -1;
-        atomicOr(status, ST_RELAXED_RESCAN);
-      }
-      __syncthreads();
+    j = s_pick;
+    if (!s_need_scan) break;
+    // Full rescan of column j over the rows not yet chosen.
+    const double* colp = a21 + (size_t)j * lda;
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = threadIdx.x; i < r; i += blockDim.x) {
+      if ((flags[i >> 5] >> (i & 31)) & 1u) continue;
+      const double v = fabs(colp[i]);
+      if (better(v, i, bv, bi)) { bv = v; bi = i; }
     }
-    if (threadIdx.x == 0) chosen[j] = s_pick;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (better(ov, oi, bv, bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
     __syncthreads();
-    if (s_pick >= 0) ++taken;
+    if (threadIdx.x == 0) {
+      double xv = red_v[0];
+      int xi = red_i[0];
+      for (int w = 1; w < nwaves; ++w)
+        if (better(red_v[w], red_i[w], xv, xi)) { xv = red_v[w]; xi = red_i[w]; }
+      const int pick = (xv >= 0.0) ? xi : -1;
+      chosen[j] = pick;
+      if (pick >= 0) {
+        flags[pick >> 5] |= 1u << (pick & 31);
+        ++s_taken;
+      }
+      atomicOr(status, ST_RELAXED_RESCAN);
+    }
+    __syncthreads();
+    ++j;
   }
+  __syncthreads();
 
   // 3. Gather the chosen signed rows into C (zero rows when none).
   for (int q = threadIdx.x; q < p * p; q += blockDim.x) {
@@ -369,7 +388,7 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
       dim3 grid(p, nch);
       relaxed_topk_kernel<<<grid, 256, 0, stream>>>(r, p, a21, lda, nch, cand, status);
     }
-    size_t lds = (size_t)p * RELAXED_TOPK * sizeof(Cand) + (size_t)p * sizeof(int);
+    size_t lds = (size_t)p * RELAXED_TOPK * sizeof(Cand) + (size_t)p * sizeof(int) + relaxed_flag_bytes(r);
     if (r > 0 && lds > 64 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void*)relaxed_select_kernel,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -463,7 +482,8 @@ int launch_compress_batch(int count, const BatchNode* nodes, int method, int max
     }
   } else if (method == CTP_RELAXED) {
     if (max_r > 0) relaxed_topk_batch_kernel<<<dim3(max_p, max_chunks, count), 256, 0, stream>>>(nodes);
-    const size_t lds = (size_t)max_p * RELAXED_TOPK * sizeof(Cand) + (size_t)max_p * sizeof(int);
+    const size_t lds =
+        (size_t)max_p * RELAXED_TOPK * sizeof(Cand) + (size_t)max_p * sizeof(int) + relaxed_flag_bytes(max_r);
     if (lds > 64 * 1024) {
       hipError_t e = hipFuncSetAttribute((const void*)relaxed_select_batch_kernel,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

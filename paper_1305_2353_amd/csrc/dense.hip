@@ -30,7 +30,8 @@
 // block step of either sweep is a dense product with coalesced columns:
 //   forward  block j: z_j = Linv_j y_j; rows below: y_R -= L(R, j) z_j
 //   backward block j: x_j = Linv_j^T z_j; rows above: z_R -= L^T(R, j) x_j
-// (one launch per block, every workgroup recomputing the small product).
+// (one launch per block, every workgroup recomputing the small product on
+// the matrix cores).
 
 #include <vector>
 
@@ -211,53 +212,88 @@ __global__ void dense_dsolve_kernel(const int* __restrict__ piv, const double* _
 constexpr int SW_THREADS = 256;
 constexpr int SW_MAXRHS = 16;
 
-// One block step of a sweep.  blk: the diagonal block; the DB x DB inverse
-// M (column-major, applied as t = M v_blk); rows of the update: the
-// DB-row chunks listed by the grid (workgroup 0 writes t back into v_blk,
-// workgroup q >= 1 updates chunk rlo + (q-1)*DB of v with the off-diagonal
-// block of F, whose column k of the block sits at F + (c0 + k) * ldf).
-// piv (forward sweep only, else null): a 2x2 pivot that straddles the
-// block boundary keeps the off-diagonal of D in L(c0 + nb, c0 + nb - 1);
-// that entry is read as 0.
-__global__ __launch_bounds__(SW_THREADS) void dense_sweep_kernel(const double* __restrict__ F, int ldf,
-                                                                 const double* __restrict__ M, int c0,
-                                                                 int nb, int rlo, int rhi,
-                                                                 const int* __restrict__ piv,
-                                                                 double* __restrict__ v, int ldv,
-                                                                 int nrhs) {
-  __shared__ double vb[SW_MAXRHS][DB];
-  __shared__ double tb[SW_MAXRHS][DB];
-  const int tid = threadIdx.x;
-  for (int q = tid; q < nrhs * DB; q += SW_THREADS) {
-    const int c = q / DB, k = q % DB;
-    vb[c][k] = k < nb ? v[(size_t)c * ldv + c0 + k] : 0.0;
+// One block step of a sweep, on the FP64 matrix cores.  The diagonal
+// block's inverse M (column-major DB x DB, applied as t = M v_blk); rows of
+// the update: the DB-row chunks listed by the grid (workgroup 0 writes t
+// back into v_blk, workgroup q >= 1 updates chunk rlo + (q-1)*DB of v with
+// the off-diagonal block of F, whose column k of the block sits at
+// F + (c0 + k) * ldf).  Both products of the step
+// -- t = M v_blk (128 x 128 by 128 x nrhs) and the update of a 128-row
+// chunk by F(chunk, blk) t -- are v_mfma_f64_16x16x4 products with the
+// right-hand sides as the 16 columns of B (nrhs <= 16, the rest zero).
+// Wave w owns row blocks 2w, 2w+1 (16 rows each) of the 128-row tile.
+typedef double d4w __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void dense_sweep_mfma_kernel(const double* __restrict__ F, int ldf,
+                                                                const double* __restrict__ M, int c0, int nb,
+                                                                int rlo, int rhi, const int* __restrict__ piv,
+                                                                double* __restrict__ v, int ldv, int nrhs) {
+  __shared__ double vb[DB][17];   // v_blk, then t, by (k, rhs)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int q = tid; q < DB * 16; q += 256) {
+    const int k = q % DB, c = q / DB;
+    vb[k][c] = (k < nb && c < nrhs) ? v[(size_t)c * ldv + c0 + k] : 0.0;
   }
   __syncthreads();
-  // t = M vb (rows i < nb)
-  for (int q = tid; q < nrhs * DB; q += SW_THREADS) {
-    const int c = q / DB, i = q % DB;
-    double s = 0.0;
-    if (i < nb)
-      for (int k = 0; k < nb; ++k) s = fma(M[(size_t)k * DB + i], vb[c][k], s);
-    tb[c][i] = s;
+  // t = M v_blk; all 64 A fragments of this lane are loaded first so that
+  // their latencies overlap
+  d4w acc[2];
+  double af[2][DB / 4];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int s = 0; s < DB / 4; ++s) af[x][s] = M[(size_t)(4 * s + fk) * DB + (2 * wave + x) * 16 + fr];
+  for (int x = 0; x < 2; ++x) acc[x] = d4w{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < DB / 4; ++s) {
+    const double b = vb[4 * s + fk][fr];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x][s], b, acc[x], 0, 0, 0);
   }
+  __syncthreads();   // every wave has read v_blk
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vb[(2 * wave + x) * 16 + fk + 4 * q][fr] = acc[x][q];
   __syncthreads();
   if (blockIdx.x == 0) {
-    for (int q = tid; q < nrhs * DB; q += SW_THREADS) {
-      const int c = q / DB, i = q % DB;
-      if (i < nb) v[(size_t)c * ldv + c0 + i] = tb[c][i];
+    for (int q = tid; q < DB * 16; q += 256) {
+      const int k = q % DB, c = q / DB;
+      if (k < nb && c < nrhs) v[(size_t)c * ldv + c0 + k] = vb[k][c];
     }
     return;
   }
+  // rows r0 .. r0+127 of the chunk: v -= F(rows, blk) t
   const int r0 = rlo + (blockIdx.x - 1) * DB;
-  const int i = r0 + (tid % DB);
-  if (i >= rhi) return;
-  const int kend = (piv && i == c0 + nb && piv[c0 + nb - 1] == PIV_2X2_FIRST) ? nb - 1 : nb;
-  for (int c = tid / DB; c < nrhs; c += SW_THREADS / DB) {
-    double s = 0.0;
-    for (int k = 0; k < kend; ++k) s = fma(F[(size_t)(c0 + k) * ldf + i], tb[c][k], s);
-    v[(size_t)c * ldv + i] -= s;
+  const bool strad = piv && nb > 0 && piv[c0 + nb - 1] == PIV_2X2_FIRST;
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int i = r0 + (2 * wave + x) * 16 + fr;
+    const int ic = i < rhi ? i : rhi - 1;
+#pragma unroll
+    for (int s = 0; s < DB / 4; ++s) {
+      const int k = 4 * s + fk;
+      const bool kv = k < nb;
+      double a = F[(size_t)(c0 + (kv ? k : 0)) * ldf + ic];
+      if (!kv || (strad && i == c0 + nb && k == nb - 1)) a = 0.0;
+      af[x][s] = a;
+    }
   }
+  for (int x = 0; x < 2; ++x) acc[x] = d4w{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < DB / 4; ++s) {
+    const double b = vb[4 * s + fk][fr];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x][s], b, acc[x], 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = r0 + (2 * wave + x) * 16 + fk + 4 * q;
+      if (i < rhi && fr < nrhs) v[(size_t)fr * ldv + i] -= acc[x][q];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -564,16 +600,16 @@ int ctp_ldlt_solve(int N, int nrhs, const double* a, int lda, const int* perm, c
     const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
     const int rlo = c0 + nb, rhi = N;
     const int chunks = (rhi - rlo + DB - 1) / DB;
-    dense_sweep_kernel<<<1 + chunks, SW_THREADS, 0, stream>>>(a, lda, linv + (size_t)j * DB * DB, c0, nb,
-                                                              rlo, rhi, piv, y, ldy, nrhs);
+    dense_sweep_mfma_kernel<<<1 + chunks, 256, 0, stream>>>(a, lda, linv + (size_t)j * DB * DB, c0, nb, rlo, rhi,
+                                                            piv, y, ldy, nrhs);
   }
   dense_dsolve_kernel<<<eg, 256, 0, stream>>>(piv, d, y, ldy, N, nrhs);
   for (int j = nbk - 1; j >= 0; --j) {     // backward: L^T x' = z, L^T in the upper triangle
     const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
     const int rlo = 0, rhi = c0;
     const int chunks = (rhi - rlo + DB - 1) / DB;
-    dense_sweep_kernel<<<1 + chunks, SW_THREADS, 0, stream>>>(a, lda, linvt + (size_t)j * DB * DB, c0, nb,
-                                                              rlo, rhi, nullptr, y, ldy, nrhs);
+    dense_sweep_mfma_kernel<<<1 + chunks, 256, 0, stream>>>(a, lda, linvt + (size_t)j * DB * DB, c0, nb, rlo, rhi,
+                                                            nullptr, y, ldy, nrhs);
   }
   dense_scatter_kernel<<<eg, 256, 0, stream>>>(y, ldy, perm, b, ldb, N, nrhs);
   hipError_t e = hipGetLastError();
