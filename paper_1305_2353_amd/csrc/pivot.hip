@@ -46,16 +46,17 @@
 //  (enough for p eliminations); pairs after the end of the loop exit at
 //  once, so the launch sequence does not depend on the data.
 
+#include <type_traits>
+
 #include "common.h"
 
 #pragma clang fp contract(off)
 
 namespace ctp {
 
-constexpr int PIV_THREADS = 1024;
-constexpr int PIV_WAVES = PIV_THREADS / 64;
+constexpr int PIV_MAX_THREADS = 1024;   // workgroup sizes 256, 512 or 1024 (template NT)
+constexpr int PIV_MAX_WAVES = PIV_MAX_THREADS / 64;
 constexpr int NSLOT = PIV_NSLOT;   // pending eliminated columns per batch
-constexpr int RCACHE = 1024;       // R rows whose multipliers are cached in LDS
 constexpr int APPLY_TILE = 64;
 
 struct PivState {
@@ -122,38 +123,60 @@ __global__ void pivot_init_kernel(PivotArgs g) {
 // decide: the pivot loop on lazily updated values
 // ---------------------------------------------------------------------------
 
+// LDS of the decide kernel.  Dynamic part (doubles): multipliers of A11
+// rows lA[NSLOT][p], pivot-column values wc[NSLOT][p] (both by position),
+// multipliers of the first rc rows of R lR[NSLOT][rc], and the two columns
+// under test, colA and colB, each p + rc values (rows of the square by
+// position, then the cached rows of R).  rc is as many R rows as fit.
+constexpr int PIV_DYN_DOUBLES = 18432;   // 144 KiB
+
+__host__ __device__ inline int pivot_rcache(int p) {
+  const int fit = (PIV_DYN_DOUBLES - (2 * NSLOT + 2) * p) / (NSLOT + 2);
+  const int rc = fit / 256 * 256;
+  return rc < 1024 ? rc : 1024;
+}
+
+// Reductions over the workgroup: every thread keeps the two largest |a| of
+// a column (values only: when the largest value occurs twice, excluding
+// either row leaves it, so no row numbers are needed) and, in the first
+// pass, the largest |a(m, j)| with its column.  Waves merge by shuffles,
+// then each wave's result goes to one of two alternating slots in LDS, so
+// one barrier per reduction suffices (the slot written by reduction k + 2
+// was last read before everybody reached reduction k + 1).  The scalars the
+// decision needs besides the maxima travel in the same slot.
 struct DecideShared {
-  double red_v[PIV_WAVES];
-  double red_v2[PIV_WAVES];
-  int red_i[PIV_WAVES];
-  int nelim, m, progress, done, nslot, action, status;
+  double v1[2][PIV_MAX_WAVES], v2[2][PIV_MAX_WAVES], rv[2][PIV_MAX_WAVES];
+  int ri[2][PIV_MAX_WAVES];
+  double sc[2][3];
+  int nelim, m, progress, done, status;
   int kind[NSLOT];
   int sk[NSLOT];
 };
 
-// LDS of the decide kernel.  Dynamic part: multipliers of A11 rows
-// lA[NSLOT][p], pivot-column values wc[NSLOT][p] (both by position) and
-// multipliers of the first rc rows of R, lR[NSLOT][rc].
 extern __shared__ double pv_dyn[];
 __shared__ DecideShared pv_sh;
 __shared__ double pv_d[2 * CTP_MAX_P];
 __shared__ int pv_perm[CTP_MAX_P];
 __shared__ int pv_piv[CTP_MAX_P];
 
-CTP_DEV double& lA(int p, int s, int i) { return pv_dyn[s * p + i]; }
-CTP_DEV double& wc(int p, int s, int j) { return pv_dyn[NSLOT * p + s * p + j]; }
-CTP_DEV double& lR(int p, int rc, int s, int i) { return pv_dyn[2 * NSLOT * p + s * rc + i]; }
+// Index helpers (the arrays are always named directly, so every access is
+// an LDS access: no generic pointers into LDS).
+CTP_DEV int lA(int p, int s, int i) { return s * p + i; }
+CTP_DEV int wc(int p, int s, int j) { return NSLOT * p + s * p + j; }
+CTP_DEV int lR(int p, int rc, int s, int i) { return 2 * NSLOT * p + s * rc + i; }
+CTP_DEV int colbuf(int p, int rc, int c) { return 2 * NSLOT * p + NSLOT * rc + c * (p + rc); }
 
-CTP_DEV double lazy_a(const PivotArgs& g, int i, int j) {
+// Lazily updated entry (i, j) of the square: the stored value minus the
+// pending updates of the ns slots of this batch.
+CTP_DEV double lazy_a(const PivotArgs& g, int ns, int i, int j) {
   double v = CM(g.T, i, j, g.lda);
   const int p = g.p;
-  const int ns = pv_sh.nslot;
   for (int s = 0; s < ns; ++s) {
     if (pv_sh.kind[s] == 1) {
-      const double prod = lA(p, s, i) * wc(p, s, j);
+      const double prod = pv_dyn[lA(p, s, i)] * pv_dyn[wc(p, s, j)];
       v = v - prod;
     } else {
-      const double upd = lA(p, s, i) * wc(p, s, j) + lA(p, s + 1, i) * wc(p, s + 1, j);
+      const double upd = pv_dyn[lA(p, s, i)] * pv_dyn[wc(p, s, j)] + pv_dyn[lA(p, s + 1, i)] * pv_dyn[wc(p, s + 1, j)];
       v = v - upd;
       ++s;
     }
@@ -161,18 +184,24 @@ CTP_DEV double lazy_a(const PivotArgs& g, int i, int j) {
   return v;
 }
 
+// Multipliers of R rows: the first rc rows keep theirs in LDS, the others
+// read them from the eliminated columns of R.  The two kinds of rows go
+// through separate loops (for_r_rows), so an access is always either an LDS
+// or a global access, never a pointer that could be both.
+template <bool CACHED>
 CTP_DEV double r_mult(const PivotArgs& g, int rc, int s, int i) {
-  return i < rc ? lR(g.p, rc, s, i) : CM(g.R, i, pv_sh.sk[s], g.ldr);
+  if (CACHED) return pv_dyn[lR(g.p, rc, s, i)];
+  return CM(g.R, i, pv_sh.sk[s], g.ldr);
 }
 
-CTP_DEV double lazy_r(const PivotArgs& g, int rc, int i, int j) {
+template <bool CACHED>
+CTP_DEV double lazy_r(const PivotArgs& g, int ns, int rc, int i, int j) {
   double v = CM(g.R, i, j, g.ldr);
   const int p = g.p;
-  const int ns = pv_sh.nslot;
   for (int s = 0; s < ns; ++s) {
     if (pv_sh.kind[s] == 1) {
-      const double lr = r_mult(g, rc, s, i);
-      const double w = wc(p, s, j);
+      const double lr = r_mult<CACHED>(g, rc, s, i);
+      const double w = pv_dyn[wc(p, s, j)];
       if (g.abs_update) {
         const double prod = lr * fabs(w);
         v = v + prod;
@@ -181,8 +210,8 @@ CTP_DEV double lazy_r(const PivotArgs& g, int rc, int i, int j) {
         v = v - prod;
       }
     } else {
-      const double l1 = r_mult(g, rc, s, i), l2 = r_mult(g, rc, s + 1, i);
-      const double w1 = wc(p, s, j), w2 = wc(p, s + 1, j);
+      const double l1 = r_mult<CACHED>(g, rc, s, i), l2 = r_mult<CACHED>(g, rc, s + 1, i);
+      const double w1 = pv_dyn[wc(p, s, j)], w2 = pv_dyn[wc(p, s + 1, j)];
       if (g.abs_update) {
         const double upd = l1 * fabs(w1) + l2 * fabs(w2);
         v = v + upd;
@@ -196,100 +225,184 @@ CTP_DEV double lazy_r(const PivotArgs& g, int rc, int i, int j) {
   return v;
 }
 
-CTP_DEV double block_max(double v) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_max(v);
-  if (lane == 0) pv_sh.red_v[wave] = v;
-  __syncthreads();
-  double r = pv_sh.red_v[0];
-  for (int w = 1; w < PIV_WAVES; ++w) r = fmax(r, pv_sh.red_v[w]);
-  __syncthreads();
-  return r;
+// This thread's rows of R: rows i = tid (mod NT), the cached ones (i < rc)
+// first.  Every loop that needs a row to stay with one thread uses this.
+template <int NT, typename F>
+CTP_DEV void for_r_rows(int rc, int r, F&& f) {
+  for (int i = threadIdx.x; i < rc; i += NT) f(i, std::true_type{});
+  for (int i = rc + threadIdx.x; i < r; i += NT) f(i, std::false_type{});
 }
 
-CTP_DEV void block_max2(double& v1, double& v2) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v1 = wave_max(v1);
-  v2 = wave_max(v2);
-  if (lane == 0) { pv_sh.red_v[wave] = v1; pv_sh.red_v2[wave] = v2; }
-  __syncthreads();
-  double r1 = pv_sh.red_v[0], r2 = pv_sh.red_v2[0];
-  for (int w = 1; w < PIV_WAVES; ++w) { r1 = fmax(r1, pv_sh.red_v[w]); r2 = fmax(r2, pv_sh.red_v2[w]); }
-  __syncthreads();
-  v1 = r1;
-  v2 = r2;
+struct Top2 {
+  double v1, v2;
+};
+
+CTP_DEV Top2 top2_empty() { return Top2{-1.0, -1.0}; }
+
+// x = |a| or NaN; a NaN never enters
+CTP_DEV void top2_insert(Top2& t, double x) {
+  x = fmax(x, -1.0);
+  t.v2 = fmax(t.v2, fmin(t.v1, x));
+  t.v1 = fmax(t.v1, x);
 }
 
-CTP_DEV int block_argmax(double v, int idx) {
+CTP_DEV void top2_merge(Top2& t, double o1, double o2) {
+  t.v2 = fmax(fmax(t.v2, o2), fmin(t.v1, o1));
+  t.v1 = fmax(t.v1, o1);
+}
+
+CTP_DEV double top2_max(const Top2& t) { return t.v1 > 0.0 ? t.v1 : 0.0; }
+
+// largest value once one entry of value x is taken out (0 when none is left)
+CTP_DEV double top2_excluding(const Top2& t, double x) {
+  const double v = x == t.v1 ? t.v2 : t.v1;
+  return v > 0.0 ? v : 0.0;
+}
+
+CTP_DEV bool pv_better(double va, int ia, double vb, int ib) { return va > vb || (va == vb && ia < ib); }
+
+// This thread's share of column `col` of the uneliminated trapezoid: rows
+// nelim..p-1 of the square except row `col`, then every row of R.  The
+// values of the square's rows and of the cached R rows are kept in the
+// column buffer at `cb`.
+template <int NT>
+CTP_DEV void col_scan(const PivotArgs& g, int ns, int rc, int nelim, int col, int cb, Top2& t) {
+  for (int i = nelim + threadIdx.x; i < g.p; i += NT) {
+    if (i == col) continue;
+    const double x = lazy_a(g, ns, i, col);
+    pv_dyn[cb + i] = x;
+    top2_insert(t, fabs(x));
+  }
+  for (int i = threadIdx.x; i < rc; i += NT) {
+    const double x = lazy_r<true>(g, ns, rc, i, col);
+    pv_dyn[cb + g.p + i] = x;
+    top2_insert(t, fabs(x));
+  }
+  for (int i = rc + threadIdx.x; i < g.r; i += NT) top2_insert(t, fabs(lazy_r<false>(g, ns, rc, i, col)));
+}
+
+// Workgroup reduction of a column's two largest (and, with ARG, of the
+// partner search); the caller reads the slot's scalars, then flips the slot.
+template <int NT, bool ARG>
+CTP_DEV void reduce_pass(Top2& t, double& rv, int& ri, int slot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int off = 32; off > 0; off >>= 1) {
-    double ov = __shfl_xor(v, off, 64);
-    int oi = __shfl_xor(idx, off, 64);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    const double o1 = __shfl_xor(t.v1, off, 64), o2 = __shfl_xor(t.v2, off, 64);
+    top2_merge(t, o1, o2);
+    if (ARG) {
+      const double ov = __shfl_xor(rv, off, 64);
+      const int oi = __shfl_xor(ri, off, 64);
+      if (pv_better(ov, oi, rv, ri)) {
+        rv = ov;
+        ri = oi;
+      }
+    }
   }
-  if (lane == 0) { pv_sh.red_v[wave] = v; pv_sh.red_i[wave] = idx; }
-  __syncthreads();
-  double bv = pv_sh.red_v[0];
-  int bi = pv_sh.red_i[0];
-  for (int w = 1; w < PIV_WAVES; ++w) {
-    double ov = pv_sh.red_v[w];
-    int oi = pv_sh.red_i[w];
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  if (lane == 0) {
+    pv_sh.v1[slot][wave] = t.v1;
+    pv_sh.v2[slot][wave] = t.v2;
+    if (ARG) {
+      pv_sh.rv[slot][wave] = rv;
+      pv_sh.ri[slot][wave] = ri;
+    }
   }
   __syncthreads();
-  return bi;
+  // lane w of every wave takes wave w's partial, a butterfly over the first
+  // NT / 64 lanes merges them, lane 0's result is broadcast
+  constexpr int NW = NT / 64;
+  Top2 u = top2_empty();
+  double bv = -1.0;
+  int bi = 0x7fffffff;
+  if (lane < NW) {
+    u.v1 = pv_sh.v1[slot][lane];
+    u.v2 = pv_sh.v2[slot][lane];
+    if (ARG) {
+      bv = pv_sh.rv[slot][lane];
+      bi = pv_sh.ri[slot][lane];
+    }
+  }
+  for (int off = NW / 2; off > 0; off >>= 1) {
+    const double o1 = __shfl_xor(u.v1, off, 64), o2 = __shfl_xor(u.v2, off, 64);
+    top2_merge(u, o1, o2);
+    if (ARG) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (pv_better(ov, oi, bv, bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+  }
+  t.v1 = __shfl(u.v1, 0, 64);
+  t.v2 = __shfl(u.v2, 0, 64);
+  if (ARG) {
+    rv = __shfl(bv, 0, 64);
+    ri = __shfl(bi, 0, 64);
+  }
 }
 
-// max |a(i, col)| over uneliminated rows i in [nelim, p) \ {x1, x2} of the
-// square and all rows of R: this thread's partial.
-CTP_DEV double col_partial(const PivotArgs& g, int rc, int nelim, int col, int x1, int x2) {
-  double v = 0.0;
-  for (int i = nelim + threadIdx.x; i < g.p; i += PIV_THREADS)
-    if (i != x1 && i != x2) v = fmax(v, fabs(lazy_a(g, i, col)));
-  for (int i = threadIdx.x; i < g.r; i += PIV_THREADS) v = fmax(v, fabs(lazy_r(g, rc, i, col)));
-  return v;
+// Symmetric interchanges (a0, b0) then (a1, b1): afterwards position x
+// holds what was at swap_src(x).  A single interchange passes a1 = b1.
+struct SwapPlan {
+  int x[4];
+  int src[4];
+};
+
+CTP_DEV int swap_src(int a0, int b0, int a1, int b1, int x) {
+  const int y = x == a1 ? b1 : x == b1 ? a1 : x;
+  return y == a0 ? b0 : y == b0 ? a0 : y;
 }
 
-// Symmetric interchange of positions a and b: rows then columns of the
-// square (stored values, L rows of eliminated columns), the rows of the
-// pending multiplier / pivot-column vectors, the columns of R, perm.
-CTP_DEV void sym_swap(const PivotArgs& g, int a, int b) {
-  if (a == b) return;
+CTP_DEV SwapPlan swap_plan(int a0, int b0, int a1, int b1) {
+  SwapPlan s;
+  s.x[0] = a0;
+  s.x[1] = b0;
+  s.x[2] = a1;
+  s.x[3] = b1;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s.src[q] = swap_src(a0, b0, a1, b1, s.x[q]);
+  return s;
+}
+
+// Moves the entries at the plan's positions of one line (a row or a column,
+// reached through ld / st): every value is read before any is written.
+template <typename V, typename Ld, typename St>
+CTP_DEV void permute_line(const SwapPlan& s, Ld&& ld, St&& st) {
+  V v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = ld(s.x[q]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (s.src[q] == s.x[q]) continue;
+    V val = v[3];
+#pragma unroll
+    for (int e = 2; e >= 0; --e)
+      if (s.src[q] == s.x[e]) val = v[e];
+    st(s.x[q], val);
+  }
+}
+
+// Row half of the interchanges: the rows of the square (stored values and
+// the L rows of eliminated columns), the rows of the pending multiplier and
+// pivot-column vectors, perm.  The column half runs inside the elimination
+// loops, by the thread that owns the row.
+template <int NT>
+CTP_DEV void swap_rows(const PivotArgs& g, int ns, const SwapPlan& s) {
   const int p = g.p;
-  for (int j = threadIdx.x; j < p; j += PIV_THREADS) {
-    const double x = CM(g.T, a, j, g.lda), y = CM(g.T, b, j, g.lda);
-    CM(g.T, a, j, g.lda) = y;
-    CM(g.T, b, j, g.lda) = x;
+  for (int j = threadIdx.x; j < p; j += NT)
+    permute_line<double>(s, [&](int x) { return CM(g.T, x, j, g.lda); },
+                         [&](int x, double v) { CM(g.T, x, j, g.lda) = v; });
+  for (int q = threadIdx.x; q < ns; q += NT) {
+    permute_line<double>(s, [&](int x) { return pv_dyn[lA(p, q, x)]; },
+                         [&](int x, double v) { pv_dyn[lA(p, q, x)] = v; });
+    permute_line<double>(s, [&](int x) { return pv_dyn[wc(p, q, x)]; },
+                         [&](int x, double v) { pv_dyn[wc(p, q, x)] = v; });
   }
-  const int ns = pv_sh.nslot;
-  for (int s = threadIdx.x; s < ns; s += PIV_THREADS) {
-    double x = lA(p, s, a);
-    lA(p, s, a) = lA(p, s, b);
-    lA(p, s, b) = x;
-    x = wc(p, s, a);
-    wc(p, s, a) = wc(p, s, b);
-    wc(p, s, b) = x;
-  }
-  if (threadIdx.x == 0) {
-    const int t = pv_perm[a];
-    pv_perm[a] = pv_perm[b];
-    pv_perm[b] = t;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < p; i += PIV_THREADS) {
-    const double x = CM(g.T, i, a, g.lda), y = CM(g.T, i, b, g.lda);
-    CM(g.T, i, a, g.lda) = y;
-    CM(g.T, i, b, g.lda) = x;
-  }
-  for (int i = threadIdx.x; i < g.r; i += PIV_THREADS) {
-    const double x = CM(g.R, i, a, g.ldr), y = CM(g.R, i, b, g.ldr);
-    CM(g.R, i, a, g.ldr) = y;
-    CM(g.R, i, b, g.ldr) = x;
-  }
-  __syncthreads();
+  if (threadIdx.x == 0)
+    permute_line<int>(s, [&](int x) { return pv_perm[x]; }, [&](int x, int v) { pv_perm[x] = v; });
 }
 
-enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT, ACT_PASS, ACT_STOP, ACT_FALLBACK };
+enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT };
 
 // Non-singularity part of the 2x2 test alone (Section 2): the scaled
 // determinant is clear of cancellation and of small.
@@ -303,27 +416,33 @@ CTP_DEV bool det_ok(double att, double atm, double amm, double small) {
   return fabs(det) > fmax(fmax(small, fabs(det0) / 2.0), fabs(det1) / 2.0);
 }
 
+// The pivot loop.  Its state (nelim, m, progress, the number of pending
+// slots) is uniform: every thread takes the same decisions from the same
+// reduced values and keeps its own copy, so a rejected candidate costs only
+// its reductions.  Barriers per elimination: one between the row and the
+// column half of the interchanges, one at the end.
+template <int NT>
 CTP_DEV void pivot_decide_body(const PivotArgs& g) {
-  DecideShared& sh = pv_sh;
   const int p = g.p;
-  const int rc = min(g.r, RCACHE);
+  const int rc = min(g.r, pivot_rcache(p));
+  const int cA = colbuf(p, rc, 0), cB = colbuf(p, rc, 1);
 
   PivState* st = g.st;
   if (threadIdx.x == 0) {
-    sh.nelim = st->nelim;
-    sh.m = st->m;
-    sh.progress = st->progress;
-    sh.done = st->done;
-    sh.status = 0;
-    sh.nslot = 0;
+    pv_sh.nelim = st->nelim;
+    pv_sh.m = st->m;
+    pv_sh.progress = st->progress;
+    pv_sh.done = st->done;
+    pv_sh.status = 0;
   }
   __syncthreads();
-  if (sh.done) {
+  if (pv_sh.done) {
     // the previous apply consumed the last batch
     if (threadIdx.x == 0) st->nslot = 0;
     return;
   }
-  for (int k = threadIdx.x; k < p; k += PIV_THREADS) {
+  int nelim = pv_sh.nelim, m = pv_sh.m, progress = pv_sh.progress;
+  for (int k = threadIdx.x; k < p; k += NT) {
     pv_perm[k] = g.perm[k];
     pv_piv[k] = g.piv[k];
     pv_d[2 * k] = g.d[2 * k];
@@ -332,62 +451,96 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
   __syncthreads();
 
   const double inv_u = 1.0 / g.u;
-  bool batch_full = false;
-  while (true) {
-    const int nelim = sh.nelim;
-    const int m = sh.m;
-    if (nelim >= p || batch_full) break;
+  int ns = 0;     // pending slots of this batch
+  int slot = 0;   // alternating LDS slot of the reductions
+  while (nelim < p && ns < NSLOT - 1) {
     int action = ACT_NONE;
     int t = -1;
     int mc = m;        // position the action applies to
-    bool fb = false;   // root fallback step
+    bool fb = false;   // root fallback step (no column buffers)
+    double d1 = 0.0, d21 = 0.0, d2 = 0.0;   // pivot: d1 (1x1) or [d1 d21; d21 d2]
     if (m >= p) {
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        if (!sh.progress) sh.action = g.root ? ACT_FALLBACK : ACT_STOP;
-        else { sh.action = ACT_PASS; sh.progress = 0; sh.m = nelim; }
+      if (progress) {
+        // end of a pass that eliminated something: a new pass
+        progress = 0;
+        m = nelim;
+        continue;
       }
-      __syncthreads();
-      if (sh.action == ACT_STOP) break;
-      if (sh.action == ACT_PASS) continue;
+      if (!g.root) break;
       // A pass without progress in the last panel: eliminate the column at
       // nelim regardless of u (1x1 unless below small, else a 2x2 with the
       // next column if its determinant is safely nonzero, else zero).
       fb = true;
       const int k = nelim;
-      const double akk = lazy_a(g, k, k);
+      const double akk = lazy_a(g, ns, k, k);
+      double a21 = 0.0, a22 = 0.0;
+      bool two = false;
+      if (!(fabs(akk) >= g.small) && k + 1 < p) {
+        a21 = lazy_a(g, ns, k + 1, k);
+        a22 = lazy_a(g, ns, k + 1, k + 1);
+        two = det_ok(akk, a21, a22, g.small);
+      }
       if (fabs(akk) >= g.small) {
         action = ACT_1X1;
         mc = k;
-      } else if (k + 1 < p && det_ok(akk, lazy_a(g, k + 1, k), lazy_a(g, k + 1, k + 1), g.small)) {
+        d1 = akk;
+      } else if (two) {
         action = ACT_2X2;
         t = k;
         mc = k + 1;
+        d1 = akk;
+        d21 = a21;
+        d2 = a22;
       } else {
         action = ACT_ZERO;
         mc = k;
       }
-      if (threadIdx.x == 0) sh.status |= ST_ROOT_FALLBACK;
+      if (threadIdx.x == 0) pv_sh.status |= ST_ROOT_FALLBACK;
+      // every thread has read the block before its owners overwrite it
+      __syncthreads();
     } else {
-      double maxm = block_max(col_partial(g, rc, nelim, m, m, m));
-      const double amm = lazy_a(g, m, m);
+      // pass A: column m (rows other than m) into colA with its largest two,
+      // the partner search along row m, the diagonal entry (thread 0)
+      Top2 cm = top2_empty();
+      col_scan<NT>(g, ns, rc, nelim, m, cA, cm);
+      double rv = -1.0;
+      int ri = 0x7fffffff;
+      for (int j = nelim + threadIdx.x; j < m; j += NT) {
+        double x = fabs(lazy_a(g, ns, m, j));
+        if (x != x) x = -0.5;   // NaN: loses to any number, keeps t a valid index
+        if (x > rv) {
+          rv = x;
+          ri = j;
+        }
+      }
+      if (threadIdx.x == 0) pv_sh.sc[slot][0] = lazy_a(g, ns, m, m);
+      reduce_pass<NT, true>(cm, rv, ri, slot);
+      const double amm = pv_sh.sc[slot][0];
+      slot ^= 1;
+      const double maxm = top2_max(cm);
       const double colmax = fmax(fabs(amm), maxm);
-      if (threadIdx.x == 0 && !isfinite(colmax)) sh.status |= ST_NONFINITE;
+      if (threadIdx.x == 0 && !isfinite(colmax)) pv_sh.status |= ST_NONFINITE;
       if (colmax < g.small) {
         action = ACT_ZERO;
       } else if (m > nelim) {
-        double v = -1.0;
-        int idx = 0x7fffffff;
-        for (int j = nelim + threadIdx.x; j < m; j += PIV_THREADS) {
-          double x = fabs(lazy_a(g, m, j));
-          if (x != x) x = -0.5;   // NaN: loses to any number, keeps t a valid index
-          if (x > v) { v = x; idx = j; }
+        t = ri;
+        // pass B: column t (rows other than t) into colB with its largest
+        // two; a_tt (thread 0), a_mt (the owner of row m) and a_tm (read
+        // back from colA by thread 0) travel with the reduction
+        Top2 ct = top2_empty();
+        col_scan<NT>(g, ns, rc, nelim, t, cB, ct);
+        if (threadIdx.x == 0) {
+          pv_sh.sc[slot][0] = lazy_a(g, ns, t, t);
+          pv_sh.sc[slot][2] = pv_dyn[cA + t];
         }
-        t = block_argmax(v, idx);
-        double maxt = col_partial(g, rc, nelim, t, t, m);
-        double maxm2 = col_partial(g, rc, nelim, m, t, m);
-        block_max2(maxt, maxm2);
-        const double att = lazy_a(g, t, t), atm = lazy_a(g, m, t);
+        if (threadIdx.x == (m - nelim) % NT) pv_sh.sc[slot][1] = pv_dyn[cB + m];
+        double dv = -1.0;
+        int di = 0;
+        reduce_pass<NT, false>(ct, dv, di, slot);
+        const double att = pv_sh.sc[slot][0], atm = pv_sh.sc[slot][1], xtm = pv_sh.sc[slot][2];
+        slot ^= 1;
+        const double maxt = top2_excluding(ct, fabs(atm));    // rows other than t, m
+        const double maxm2 = top2_excluding(cm, fabs(xtm));   // rows other than m, t
         const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
         bool ok = false;
         if (!(big < g.small)) {
@@ -407,65 +560,104 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
             }
           }
         }
-        if (ok) action = ACT_2X2;
+        if (ok) {
+          action = ACT_2X2;
+          d1 = att;
+          d21 = atm;
+          d2 = amm;
+        }
       }
       if (action == ACT_NONE) {
         const double bound = g.u * maxm;
         action = (fabs(amm) >= bound) ? ACT_1X1 : ACT_REJECT;
+        d1 = amm;
       }
     }
-    // after an elimination: the next candidate and the progress flag (a
-    // fallback step restarts the pass and does not count as progress)
-    const int next1 = fb ? nelim + 1 : m + 1;
-    const int next2 = fb ? nelim + 2 : m + 2;
-    const int prog = fb ? 0 : 1;
-    // Every thread has read the values behind the decision before any
-    // thread starts the interchanges and writes below: without this wait a
-    // fast wave can swap rows that a slow wave is still reading, and the
-    // waves then disagree on the action.
-    __syncthreads();
+    if (action == ACT_REJECT) {
+      m = m + 1;
+      continue;
+    }
 
-    if (action == ACT_ZERO) {
-      sym_swap(g, mc, nelim);
-      const int k = nelim;
-      for (int i = k + 1 + threadIdx.x; i < p; i += PIV_THREADS) CM(g.T, i, k, g.lda) = 0.0;
-      for (int i = threadIdx.x; i < g.r; i += PIV_THREADS) CM(g.R, i, k, g.ldr) = 0.0;
+    // interchanges: (mc, k) for a 1x1 or zero pivot, (t, k) then (mc, k+1)
+    // for a 2x2 pivot
+    const int k = nelim;
+    const bool two = action == ACT_2X2;
+    const SwapPlan sp = two ? swap_plan(t, k, mc, k + 1) : swap_plan(mc, k, k, k);
+    const bool moves = sp.src[0] != sp.x[0] || sp.src[1] != sp.x[1] || sp.src[2] != sp.x[2] || sp.src[3] != sp.x[3];
+    if (moves) {
+      swap_rows<NT>(g, ns, sp);
       __syncthreads();
-      if (threadIdx.x == 0) {
-        CM(g.T, k, k, g.lda) = 0.0;
-        pv_piv[k] = PIV_ZERO;
-        pv_d[2 * k] = 0.0;
-        pv_d[2 * k + 1] = 0.0;
-        sh.nelim = nelim + 1;
-        sh.m = next1;
-        sh.progress = prog;
-        sh.status |= ST_ZERO_PIVOT;
-      }
-    } else if (action == ACT_2X2) {
-      sym_swap(g, t, nelim);
-      sym_swap(g, mc, nelim + 1);
-      const int k = nelim;
-      const int s0 = sh.nslot;
-      const double a11 = lazy_a(g, k, k), a21 = lazy_a(g, k + 1, k);
-      const double a22 = lazy_a(g, k + 1, k + 1);
-      const double s = 1.0 / fmax(fmax(fabs(a11), fabs(a21)), fabs(a22));
-      const double det = (a22 * s) * a11 - (a21 * s) * a21;
+    }
+    const int s0 = ns;
+    // 2x2 inverse (the same for every row)
+    double i11 = 0.0, i21 = 0.0, i22 = 0.0;
+    if (two) {
+      const double s = 1.0 / fmax(fmax(fabs(d1), fabs(d21)), fabs(d2));
+      const double det = (d2 * s) * d1 - (d21 * s) * d21;
       const double f = s / det;
-      const double i11 = f * a22, i21 = -(f * a21), i22 = f * a11;
-      for (int i = k + 2 + threadIdx.x; i < p; i += PIV_THREADS) {
-        const double w1 = lazy_a(g, i, k), w2 = lazy_a(g, i, k + 1);
-        const double l1 = w1 * i11 + w2 * i21;
-        const double l2 = w1 * i21 + w2 * i22;
-        CM(g.T, i, k, g.lda) = l1;
-        CM(g.T, i, k + 1, g.lda) = l2;
-        lA(p, s0, i) = l1;
-        lA(p, s0 + 1, i) = l2;
-        wc(p, s0, i) = w1;
-        wc(p, s0 + 1, i) = w2;
+      i11 = f * d2;
+      i21 = -(f * d21);
+      i22 = f * d1;
+    }
+    // the square: column half of the interchanges, then the pivot columns
+    // (pivot-column values from the column buffers: old column m, and old
+    // column t for a 2x2, at the row's old position)
+    for (int i = threadIdx.x; i < p; i += NT) {
+      if (moves)
+        permute_line<double>(sp, [&](int x) { return CM(g.T, i, x, g.lda); },
+                             [&](int x, double v) { CM(g.T, i, x, g.lda) = v; });
+      if (i < k) continue;
+      const int si = swap_src(sp.x[0], sp.x[1], sp.x[2], sp.x[3], i);
+      if (action == ACT_ZERO) {
+        CM(g.T, i, k, g.lda) = 0.0;
+      } else if (!two) {
+        if (i == k) {
+          CM(g.T, k, k, g.lda) = d1;
+        } else {
+          const double w = fb ? lazy_a(g, ns, i, k) : pv_dyn[cA + si];
+          const double l = w / d1;
+          CM(g.T, i, k, g.lda) = l;
+          pv_dyn[lA(p, s0, i)] = l;
+          pv_dyn[wc(p, s0, i)] = w;
+        }
+      } else {
+        if (i == k) {
+          CM(g.T, k, k, g.lda) = d1;
+        } else if (i == k + 1) {
+          CM(g.T, k + 1, k, g.lda) = d21;
+          CM(g.T, k + 1, k + 1, g.lda) = d2;
+        } else {
+          const double w1 = fb ? lazy_a(g, ns, i, k) : pv_dyn[cB + si];
+          const double w2 = fb ? lazy_a(g, ns, i, k + 1) : pv_dyn[cA + si];
+          const double l1 = w1 * i11 + w2 * i21;
+          const double l2 = w1 * i21 + w2 * i22;
+          CM(g.T, i, k, g.lda) = l1;
+          CM(g.T, i, k + 1, g.lda) = l2;
+          pv_dyn[lA(p, s0, i)] = l1;
+          pv_dyn[lA(p, s0 + 1, i)] = l2;
+          pv_dyn[wc(p, s0, i)] = w1;
+          pv_dyn[wc(p, s0 + 1, i)] = w2;
+        }
       }
-      const double j11 = fabs(i11), j21 = fabs(i21), j22 = fabs(i22);
-      for (int i = threadIdx.x; i < g.r; i += PIV_THREADS) {
-        const double x1 = lazy_r(g, rc, i, k), x2 = lazy_r(g, rc, i, k + 1);
+    }
+    // R: column half of the interchanges, then the pivot columns
+    const double adk = fabs(d1);
+    const double j11 = fabs(i11), j21 = fabs(i21), j22 = fabs(i22);
+    for_r_rows<NT>(rc, g.r, [&](int i, auto cached) {
+      constexpr bool C = decltype(cached)::value;
+      if (moves)
+        permute_line<double>(sp, [&](int x) { return CM(g.R, i, x, g.ldr); },
+                             [&](int x, double v) { CM(g.R, i, x, g.ldr) = v; });
+      if (action == ACT_ZERO) {
+        CM(g.R, i, k, g.ldr) = 0.0;
+      } else if (!two) {
+        const double x = (C && !fb) ? pv_dyn[cA + p + i] : lazy_r<C>(g, ns, rc, i, k);
+        const double l = g.abs_update ? x / adk : x / d1;
+        CM(g.R, i, k, g.ldr) = l;
+        if (C) pv_dyn[lR(p, rc, s0, i)] = l;
+      } else {
+        const double x1 = (C && !fb) ? pv_dyn[cB + p + i] : lazy_r<C>(g, ns, rc, i, k);
+        const double x2 = (C && !fb) ? pv_dyn[cA + p + i] : lazy_r<C>(g, ns, rc, i, k + 1);
         double l1, l2;
         if (g.abs_update) {
           l1 = x1 * j11 + x2 * j21;
@@ -476,98 +668,75 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
         }
         CM(g.R, i, k, g.ldr) = l1;
         CM(g.R, i, k + 1, g.ldr) = l2;
-        if (i < rc) {
-          lR(p, rc, s0, i) = l1;
-          lR(p, rc, s0 + 1, i) = l2;
+        if (C) {
+          pv_dyn[lR(p, rc, s0, i)] = l1;
+          pv_dyn[lR(p, rc, s0 + 1, i)] = l2;
         }
       }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        CM(g.T, k, k, g.lda) = a11;
-        CM(g.T, k + 1, k, g.lda) = a21;
-        CM(g.T, k + 1, k + 1, g.lda) = a22;
+    });
+    if (threadIdx.x == 0) {
+      if (action == ACT_ZERO) {
+        pv_piv[k] = PIV_ZERO;
+        pv_d[2 * k] = 0.0;
+        pv_d[2 * k + 1] = 0.0;
+        pv_sh.status |= ST_ZERO_PIVOT;
+      } else if (!two) {
+        pv_piv[k] = PIV_1X1;
+        pv_d[2 * k] = d1;
+        pv_d[2 * k + 1] = 0.0;
+        pv_sh.kind[s0] = 1;
+        pv_sh.sk[s0] = k;
+      } else {
         pv_piv[k] = PIV_2X2_FIRST;
         pv_piv[k + 1] = PIV_2X2_SECOND;
-        pv_d[2 * k] = a11;
-        pv_d[2 * k + 1] = a21;
-        pv_d[2 * k + 2] = a22;
+        pv_d[2 * k] = d1;
+        pv_d[2 * k + 1] = d21;
+        pv_d[2 * k + 2] = d2;
         pv_d[2 * k + 3] = 0.0;
-        sh.kind[s0] = 2;
-        sh.kind[s0 + 1] = 3;
-        sh.sk[s0] = k;
-        sh.sk[s0 + 1] = k + 1;
-        sh.nslot = s0 + 2;
-        sh.nelim = nelim + 2;
-        sh.m = next2;
-        sh.progress = prog;
+        pv_sh.kind[s0] = 2;
+        pv_sh.kind[s0 + 1] = 3;
+        pv_sh.sk[s0] = k;
+        pv_sh.sk[s0 + 1] = k + 1;
       }
-    } else if (action == ACT_1X1) {
-      sym_swap(g, mc, nelim);
-      const int k = nelim;
-      const int s0 = sh.nslot;
-      const double dk = lazy_a(g, k, k);
-      for (int i = k + 1 + threadIdx.x; i < p; i += PIV_THREADS) {
-        const double w = lazy_a(g, i, k);
-        const double l = w / dk;
-        CM(g.T, i, k, g.lda) = l;
-        lA(p, s0, i) = l;
-        wc(p, s0, i) = w;
-      }
-      const double adk = fabs(dk);
-      for (int i = threadIdx.x; i < g.r; i += PIV_THREADS) {
-        const double x = lazy_r(g, rc, i, k);
-        const double l = g.abs_update ? x / adk : x / dk;
-        CM(g.R, i, k, g.ldr) = l;
-        if (i < rc) lR(p, rc, s0, i) = l;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        CM(g.T, k, k, g.lda) = dk;
-        pv_piv[k] = PIV_1X1;
-        pv_d[2 * k] = dk;
-        pv_d[2 * k + 1] = 0.0;
-        sh.kind[s0] = 1;
-        sh.sk[s0] = k;
-        sh.nslot = s0 + 1;
-        sh.nelim = nelim + 1;
-        sh.m = next1;
-        sh.progress = prog;
-      }
-    } else {
-      __syncthreads();
-      if (threadIdx.x == 0) sh.m = m + 1;
     }
+    // after an elimination: the next candidate and the progress flag (a
+    // fallback step restarts the pass and does not count as progress)
+    const int width = action == ACT_ZERO ? 1 : two ? 2 : 1;
+    ns += action == ACT_ZERO ? 0 : width;
+    m = (fb ? nelim : m) + width;
+    nelim += width;
+    progress = fb ? 0 : 1;
     __syncthreads();
-    batch_full = sh.nslot >= NSLOT - 1;
   }
   __syncthreads();
 
   // Save the batch for the apply kernel and the loop state for the next launch.
-  const int nslot = sh.nslot;
-  for (int q = threadIdx.x; q < nslot * p; q += PIV_THREADS) g.wbuf[q] = pv_dyn[NSLOT * p + q];
-  for (int k = threadIdx.x; k < p; k += PIV_THREADS) {
+  const bool batch_full = ns >= NSLOT - 1;
+  for (int q = threadIdx.x; q < ns * p; q += NT) g.wbuf[q] = pv_dyn[NSLOT * p + q];
+  for (int k = threadIdx.x; k < p; k += NT) {
     g.perm[k] = pv_perm[k];
     g.piv[k] = pv_piv[k];
     g.d[2 * k] = pv_d[2 * k];
     g.d[2 * k + 1] = pv_d[2 * k + 1];
   }
   if (threadIdx.x == 0) {
-    const bool finished = sh.nelim >= p || !batch_full;
-    st->nelim = sh.nelim;
-    st->m = sh.m;
-    st->progress = sh.progress;
+    const bool finished = nelim >= p || !batch_full;
+    st->nelim = nelim;
+    st->m = m;
+    st->progress = progress;
     st->done = finished;
-    st->nslot = nslot;
+    st->nslot = ns;
     for (int s = 0; s < NSLOT; ++s) {
-      st->slot_k[s] = sh.sk[s];
-      st->slot_kind[s] = s < nslot ? sh.kind[s] : 0;
+      st->slot_k[s] = pv_sh.sk[s];
+      st->slot_kind[s] = s < ns ? pv_sh.kind[s] : 0;
     }
-    *g.nelim_out = sh.nelim;
-    if (sh.status) atomicOr(g.status, sh.status);
+    *g.nelim_out = nelim;
+    if (pv_sh.status) atomicOr(g.status, pv_sh.status);
   }
 }
 
-__global__ __launch_bounds__(PIV_THREADS) void pivot_decide_kernel(PivotArgs g) { pivot_decide_body(g); }
+template <int NT>
+__global__ __launch_bounds__(NT) void pivot_decide_kernel(PivotArgs g) { pivot_decide_body<NT>(g); }
 
 // ---------------------------------------------------------------------------
 // apply: materialise the pending batch on the trailing square and on R
@@ -682,12 +851,13 @@ __global__ __launch_bounds__(256) void pivot_apply_kernel(PivotArgs g) {
 
 __shared__ int pw_kind[NSLOT], pw_sk[NSLOT], pw_info[3];
 
+template <int NT>
 CTP_DEV void pivot_factor_wg_body(const PivotArgs& g) {
-  pivot_init_body(g, threadIdx.x, PIV_THREADS);
+  pivot_init_body(g, threadIdx.x, NT);
   __syncthreads();
   const int rounds = g.p / (NSLOT - 1) + 2;
   for (int q = 0; q < rounds; ++q) {
-    pivot_decide_body(g);
+    pivot_decide_body<NT>(g);
     __syncthreads();
     if (threadIdx.x == 0) {
       pw_info[0] = g.st->nslot;
@@ -702,7 +872,7 @@ CTP_DEV void pivot_factor_wg_body(const PivotArgs& g) {
     const int nslot = pw_info[0], nelim = pw_info[1], done = pw_info[2];
     if (nslot > 0) {
       const int tiles = pivot_apply_tiles(g, nelim);
-      for (int b = threadIdx.x / 256; b < tiles; b += PIV_THREADS / 256)
+      for (int b = threadIdx.x / 256; b < tiles; b += NT / 256)
         pivot_apply_tile(g, b, threadIdx.x % 256, nslot, nelim, pw_kind, pw_sk);
     }
     __syncthreads();
@@ -710,14 +880,29 @@ CTP_DEV void pivot_factor_wg_body(const PivotArgs& g) {
   }
 }
 
-__global__ __launch_bounds__(PIV_THREADS) void pivot_factor_wg_kernel(PivotArgs g) { pivot_factor_wg_body(g); }
+template <int NT>
+__global__ __launch_bounds__(NT) void pivot_factor_wg_kernel(PivotArgs g) { pivot_factor_wg_body<NT>(g); }
 
 // one workgroup per supernode of a batch
-__global__ __launch_bounds__(PIV_THREADS) void pivot_factor_batch_kernel(const PivotArgs* __restrict__ args,
-                                                                          int count) {
+template <int NT>
+__global__ __launch_bounds__(NT) void pivot_factor_batch_kernel(const PivotArgs* __restrict__ args, int count) {
   if ((int)blockIdx.x >= count) return;
   const PivotArgs g = args[blockIdx.x];
-  pivot_factor_wg_body(g);
+  pivot_factor_wg_body<NT>(g);
+}
+
+// Workgroup size of the search: enough threads for one entry of a column
+// per thread, at least 256 (the apply works on tiles of 256 threads).
+inline int pivot_threads(int p, int r) {
+  const int rc = pivot_rcache(p);
+  const int rows = p + (r < rc ? r : rc);
+  return rows <= 256 ? 256 : rows <= 512 ? 512 : 1024;
+}
+
+template <typename K>
+static hipError_t pivot_lds_attr(K kern, size_t lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 size_t pivot_lds_bytes(int p, int r);
@@ -809,19 +994,33 @@ int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags
 int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipStream_t stream) {
   const size_t lds = pivot_lds_bytes(max_p, max_r);
   if (max_p > CTP_MAX_P || lds + 16 * 1024 > 160 * 1024) return -2;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)pivot_factor_batch_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  const PivotArgs* a = static_cast<const PivotArgs*>(pargs);
+  hipError_t e0;
+  switch (pivot_threads(max_p, max_r)) {
+    case 256:
+      e0 = pivot_lds_attr(pivot_factor_batch_kernel<256>, lds);
+      if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
+      pivot_factor_batch_kernel<256><<<count, 256, lds, stream>>>(a, count);
+      break;
+    case 512:
+      e0 = pivot_lds_attr(pivot_factor_batch_kernel<512>, lds);
+      if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
+      pivot_factor_batch_kernel<512><<<count, 512, lds, stream>>>(a, count);
+      break;
+    default:
+      e0 = pivot_lds_attr(pivot_factor_batch_kernel<1024>, lds);
+      if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
+      pivot_factor_batch_kernel<1024><<<count, 1024, lds, stream>>>(a, count);
+      break;
   }
-  pivot_factor_batch_kernel<<<count, PIV_THREADS, lds, stream>>>(static_cast<const PivotArgs*>(pargs), count);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
 
 size_t pivot_lds_bytes(int p, int r) {
-  const int rc = r < RCACHE ? r : RCACHE;
-  return (size_t)NSLOT * p * sizeof(double) * 2 + (size_t)NSLOT * rc * sizeof(double);
+  const int rcap = pivot_rcache(p);
+  const int rc = r < rcap ? r : rcap;
+  return ((size_t)2 * NSLOT * p + (size_t)NSLOT * rc + 2 * ((size_t)p + rc)) * sizeof(double);
 }
 
 int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, int abs_update,
@@ -835,21 +1034,26 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
   g.wbuf = wbuf;
   const size_t lds = pivot_lds_bytes(p, r);
   if (p > CTP_MAX_P || lds + 16 * 1024 > 160 * 1024) return -2;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)pivot_decide_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
-  }
+  const int nt = pivot_threads(p, r);
+  hipError_t e0 = hipSuccess;
   if (one_wg) {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)pivot_factor_wg_kernel,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+    if (nt == 256) {
+      e0 = pivot_lds_attr(pivot_factor_wg_kernel<256>, lds);
+      if (e0 == hipSuccess) pivot_factor_wg_kernel<256><<<1, 256, lds, stream>>>(g);
+    } else if (nt == 512) {
+      e0 = pivot_lds_attr(pivot_factor_wg_kernel<512>, lds);
+      if (e0 == hipSuccess) pivot_factor_wg_kernel<512><<<1, 512, lds, stream>>>(g);
+    } else {
+      e0 = pivot_lds_attr(pivot_factor_wg_kernel<1024>, lds);
+      if (e0 == hipSuccess) pivot_factor_wg_kernel<1024><<<1, 1024, lds, stream>>>(g);
     }
-    pivot_factor_wg_kernel<<<1, PIV_THREADS, lds, stream>>>(g);
+    if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
   }
+  e0 = nt == 256 ? pivot_lds_attr(pivot_decide_kernel<256>, lds)
+                 : nt == 512 ? pivot_lds_attr(pivot_decide_kernel<512>, lds) : pivot_lds_attr(pivot_decide_kernel<1024>, lds);
+  if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
   const size_t sq = (size_t)p * p;
   const unsigned init_blocks = (unsigned)std::min<size_t>((sq + 255) / 256 + 1, 2048);
   pivot_init_kernel<<<init_blocks, 256, 0, stream>>>(g);
@@ -858,7 +1062,9 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
   // every full batch holds at least NSLOT-1 eliminated columns
   const int rounds = p / (NSLOT - 1) + 2;
   for (int q = 0; q < rounds; ++q) {
-    pivot_decide_kernel<<<1, PIV_THREADS, lds, stream>>>(g);
+    if (nt == 256) pivot_decide_kernel<256><<<1, 256, lds, stream>>>(g);
+    else if (nt == 512) pivot_decide_kernel<512><<<1, 512, lds, stream>>>(g);
+    else pivot_decide_kernel<1024><<<1, 1024, lds, stream>>>(g);
     if (apply_blocks > 0) pivot_apply_kernel<<<apply_blocks, 256, 0, stream>>>(g);
   }
   hipError_t e = hipGetLastError();
