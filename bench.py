@@ -37,10 +37,12 @@ BLOCK_ROWS = 4096
 
 # HBM bytes per Form launch from two rocprofv3 --pmc runs (FETCH_SIZE scaled by
 # the 1.9997 read factor measured on a plain copy of known size, WRITE_SIZE
-# unscaled), valid only for the kernel source they were measured on.
+# unscaled): 2.416 GB read + 1.584 GB written on average over the 25 launches
+# of the n=100000, p=512 step, valid only for the kernel source they were
+# measured on.
 FORM_COUNTERS = {
-    "source_sha256": None,
-    "hbm_bytes_per_launch": None,
+    "source_sha256": "f18d303a3da0a99d18242d92ebc9bb935a89643e831970ec9af9d40b78e831d1",
+    "hbm_bytes_per_launch": 3999677343,
     "n": 100000, "p": 512,
 }
 
@@ -220,6 +222,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-supernode section")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--dense-n", type=int, default=16384)
+    ap.add_argument("--section", default="all", choices=["all", "supernode", "dense", "batch"],
+                    help="run one part alone (for profiling): the supernode step (with the TPP "
+                         "comparison unless --no-tpp), the dense section or the batch section")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -233,6 +238,14 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.section == "dense":
+        print(json.dumps({"dense": dense_section(args.dense_n)}), flush=True)
+        return
+    if args.section == "batch":
+        print(json.dumps({"batch": batch_section(args.batch_count)}), flush=True)
+        return
+    if args.section == "supernode":
+        args.no_dense = args.no_batch = True
     n, p = args.n, args.p
     if (n, p) == (100000, 512):
         A = large_supernode(args.seed)
