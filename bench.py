@@ -207,6 +207,54 @@ def batch_section(count=4096, seed=0, method="relaxed", reps=3):
             "autotune": tune["best"], "graph": True}
 
 
+def autograd_section(S=256, N=1024, nrhs=4, pw=256, seed=0, reps=3):
+    """Batched differentiable solve x = A^-1 b of S systems Q diag(lam) Q^T
+    (|lam| in [1e-2, 1]) with loss sum(w * x): forward = batched
+    factorization + solve, backward = batched adjoint (bbar = A^-1 xbar,
+    Abar = -sym(bbar x^T)).  Median of `reps` runs after one warm-up."""
+    import torch
+    from paper_1305_2353_amd.autograd import ldlt_solve
+    from workloads import dense_indefinite_batch_torch
+
+    A0, B0 = dense_indefinite_batch_torch(S, N, seed=seed, lam_lo=1e-2, nrhs=nrhs)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed + 1)
+    W = torch.randn(B0.shape, dtype=torch.float64, device="cuda", generator=g)
+    stream = torch.cuda.current_stream()
+
+    def run():
+        A = A0.clone().requires_grad_(True)
+        B = B0.clone().requires_grad_(True)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        torch.cuda.synchronize()
+        e[0].record(stream)
+        X = ldlt_solve(A, B, pw=pw)
+        loss = (W * X).sum()
+        e[1].record(stream)
+        loss.backward()
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        return e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), X.detach()
+
+    run()
+    fw, bw = [], []
+    for _ in range(reps):
+        f_ms, b_ms, X = run()
+        fw.append(f_ms)
+        bw.append(b_ms)
+    fwd, bwd = sorted(fw)[len(fw) // 2], sorted(bw)[len(bw) // 2]
+    # backward error of every system (infinity norms, worst right-hand side)
+    R = B0 - torch.bmm(A0, X)
+    anorm = A0.abs().sum(dim=2).amax(dim=1)
+    den = anorm[:, None] * X.abs().amax(dim=1) + B0.abs().amax(dim=1)
+    berr = float((R.abs().amax(dim=1) / den).max().item())
+    flops = S * N ** 3 / 3.0
+    return {"workload": f"{S} systems N={N} Q diag(lam) Q^T, |lam| in [1e-2,1], {nrhs} RHS, panels of {pw}, "
+                        f"relaxed u=0.01: batched factor+solve (forward) and adjoint (backward)",
+            "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
+            "factor_gflops": round(flops / (fwd * 1e-3) / 1e9, 1), "bwd_err_max": berr}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,7 +270,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-supernode section")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--dense-n", type=int, default=16384)
-    ap.add_argument("--section", default="all", choices=["all", "supernode", "dense", "batch"],
+    ap.add_argument("--no-autograd", action="store_true", help="skip the batched autograd section")
+    ap.add_argument("--section", default="all", choices=["all", "supernode", "dense", "batch", "autograd"],
                     help="run one part alone (for profiling): the supernode step (with the TPP "
                          "comparison unless --no-tpp), the dense section or the batch section")
     args = ap.parse_args()
@@ -244,8 +293,11 @@ def main():
     if args.section == "batch":
         print(json.dumps({"batch": batch_section(args.batch_count)}), flush=True)
         return
+    if args.section == "autograd":
+        print(json.dumps({"autograd": autograd_section()}), flush=True)
+        return
     if args.section == "supernode":
-        args.no_dense = args.no_batch = True
+        args.no_dense = args.no_batch = args.no_autograd = True
     n, p = args.n, args.p
     if (n, p) == (100000, 512):
         A = large_supernode(args.seed)
@@ -366,6 +418,9 @@ def main():
 
     if not args.no_dense:
         result["dense"] = dense_section(args.dense_n)
+
+    if not args.no_autograd:
+        result["autograd"] = autograd_section()
 
     if not args.no_batch:
         del S, pristine, a, work

@@ -94,6 +94,10 @@ extern "C" {
 #define CTP_FLAG_ONE_WG 2u /* run the whole pivot search in one workgroup (decide
                               and apply in the same kernel, no per-batch
                               launches); same results, bit for bit */
+#define CTP_FLAG_S_SUBTRACT 8u /* batches: the Form subtracts L21 D L21^T from the lower
+                              triangle held at s + s_off (ld lds) instead of storing
+                              it -- the trailing update of a right-looking
+                              factorization; not with CTP_FLAG_S_TILED */
 
 #define CTP_ERR_HIP_BASE (-1000)
 #define CTP_ERR_PANEL_TOO_WIDE (-900)  /* dense: delays grew a panel past CTP_MAX_P */
@@ -313,6 +317,49 @@ int ctp_ldlt_adjoint(int N, int nrhs, const double* a, int lda, const int* perm,
                      const double* d, const double* x, int ldx, double* xbar, int ldxb, double* abar,
                      int ldg, const ctp_opts* opts, int pw, void* work, size_t lwork,
                      hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batches of dense systems: count independent symmetric indefinite
+ * matrices of order N, system s at a + s * stride (column-major, lda >= N,
+ * stride >= lda * N when count > 1), each factorized as ctp_ldlt_dense
+ * does (FP64 trailing updates: opts->prec must be 0; rules strict, relaxed
+ * or restricted).  Every panel step runs for all systems at once: one
+ * ctp_supernode_batched call for the panels with rows below them (the Form
+ * subtracted into the trailing matrices, CTP_FLAG_S_SUBTRACT) and one with
+ * CTP_FLAG_ROOT for the systems at their last panel, then the per-system
+ * bookkeeping; the host reads the nelim of every system back once per
+ * step.  Pivots, L and D of each system are those ctp_ldlt_dense computes.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for the three calls below (one workspace serves the
+ * factorization and the later solves / adjoints of the same batch). */
+int ctp_dense_batched_workspace_size(int count, int N, int pw, const ctp_opts* opts, size_t* bytes);
+
+/* perm, piv: count x N ints (system s at s * N); d: count x 2N doubles;
+ * status: count device ints (OR of each system's panel status bits);
+ * nsteps: host int (may be NULL), panel steps taken.  Synchronizes the
+ * stream once per step.  Errors: -1..-14 argument k,
+ * CTP_ERR_PANEL_TOO_WIDE, batched supernode errors passed through. */
+int ctp_ldlt_dense_batched(int count, int N, int pw, double* a, int lda, long long stride,
+                           const ctp_opts* opts, int* perm, int* piv, double* d, int* status,
+                           int* nsteps, void* work, size_t lwork, hipStream_t stream);
+
+/* b <- A^-1 b for every system (nrhs <= 16 columns each; system s's
+ * right-hand sides at b + s * bstride, ldb), with the factors and the
+ * workspace of ctp_ldlt_dense_batched.  FP64. */
+int ctp_ldlt_solve_batched(int count, int N, int nrhs, const double* a, int lda, long long stride,
+                           const int* perm, const int* piv, const double* d, double* b, int ldb,
+                           long long bstride, const ctp_opts* opts, int pw, void* work, size_t lwork,
+                           hipStream_t stream);
+
+/* ctp_ldlt_adjoint for every system: xbar (overwritten by bbar) at
+ * xbar + s * xbstride, x at x + s * xstride, Abar (full, symmetric) at
+ * abar + s * gstride with ld ldg. */
+int ctp_ldlt_adjoint_batched(int count, int N, int nrhs, const double* a, int lda, long long stride,
+                             const int* perm, const int* piv, const double* d, const double* x, int ldx,
+                             long long xstride, double* xbar, int ldxb, long long xbstride, double* abar,
+                             int ldg, long long gstride, const ctp_opts* opts, int pw, void* work,
+                             size_t lwork, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,7 @@ int launch_compress_batch(int count, const BatchNode* nodes, int method, int max
 int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipStream_t stream);
 int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream);
 int launch_schur_batch(int count, const BatchNode* nodes, int method, long long total, int tiled,
-                       unsigned int* counter, int variant, int workgroups, hipStream_t stream);
+                       int subtract, unsigned int* counter, int variant, int workgroups, hipStream_t stream);
 
 __global__ void clear_status_kernel(int* status) { *status = 0; }
 
@@ -235,6 +235,7 @@ int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info
   if (!info || info->count != count) return -3;
   if (count > 0 && (!panels || !perm || !piv || !d || !nelim || !status)) return -4;
   if (check_opts(opts) || opts->method == CTP_TPP) return -11;
+  if ((opts->flags & CTP_FLAG_S_SUBTRACT) && (opts->flags & CTP_FLAG_S_TILED)) return -11;
   if (!work || lwork < info->work_bytes) return -12;
   if (count == 0) return 0;
   BatchNode* bn = nullptr;
@@ -251,7 +252,8 @@ int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info
   rc = launch_solve_batch(count, bn, opts->method, info->max_p, info->max_r, stream);
   if (rc) return rc;
   if (s && info->tiles > 0)
-    rc = launch_schur_batch(count, bn, opts->method, info->tiles, (opts->flags & CTP_FLAG_S_TILED) ? 1 : 0, counter,
+    rc = launch_schur_batch(count, bn, opts->method, info->tiles, (opts->flags & CTP_FLAG_S_TILED) ? 1 : 0,
+                            (opts->flags & CTP_FLAG_S_SUBTRACT) ? 1 : 0, counter,
                             opts->tile, info->form_workgroups, stream);
   return rc;
 }

@@ -33,6 +33,7 @@
 // (one launch per block, every workgroup recomputing the small product on
 // the matrix cores).
 
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -47,6 +48,14 @@ size_t lowp_ops_bytes(int r, int kmax);
 
 constexpr int DB = 128;   // diagonal block of the solve
 
+// Per-system strides (elements) of a batch of systems, system = blockIdx.z;
+// all zero for one system.  a: matrix / factors; v: perm and piv (ints);
+// d: D; y: solve vectors; b: right-hand sides (and xbar); x: the forward
+// solution; g: Abar; w: the system's block of the workspace (doubles).
+struct DZ {
+  long long a = 0, v = 0, d = 0, y = 0, b = 0, x = 0, g = 0, w = 0;
+};
+
 // ---------------------------------------------------------------------------
 // panel bookkeeping
 // ---------------------------------------------------------------------------
@@ -60,6 +69,25 @@ __global__ __launch_bounds__(256) void dense_perm_left_kernel(double* a, int lda
   for (int q = threadIdx.x; q < pe; q += blockDim.x) col[q] = c[perm_p[q]];
   __syncthreads();
   for (int q = threadIdx.x; q < pe; q += blockDim.x) c[q] = col[q];
+}
+
+// One panel step of a batch of systems: system s (blockIdx.y) has its
+// panel at k0 with pe columns; slot indexes its nelim in the step's array.
+struct DenseStep {
+  int k0, pe, active, slot;
+};
+
+__global__ __launch_bounds__(256) void dense_perm_left_batch_kernel(double* a, int lda, long long stride,
+                                                                    const DenseStep* __restrict__ steps,
+                                                                    const int* __restrict__ pperm) {
+  __shared__ double col[CTP_MAX_P];
+  const DenseStep st = steps[blockIdx.y];
+  if (!st.active || (int)blockIdx.x >= st.k0) return;
+  const int* perm_p = pperm + (size_t)blockIdx.y * CTP_MAX_P;
+  double* c = a + (size_t)blockIdx.y * stride + (size_t)blockIdx.x * lda + st.k0;
+  for (int q = threadIdx.x; q < st.pe; q += blockDim.x) col[q] = c[perm_p[q]];
+  __syncthreads();
+  for (int q = threadIdx.x; q < st.pe; q += blockDim.x) c[q] = col[q];
 }
 
 // Global permutation, pivot types and D of the panel's eliminated columns.
@@ -80,9 +108,37 @@ __global__ __launch_bounds__(512) void dense_bookkeep_kernel(int k0, int pe, con
   }
 }
 
-__global__ void dense_iota_kernel(int* gperm, int N) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) gperm[i] = i;
+// Same, one workgroup per system of a batch.
+__global__ __launch_bounds__(512) void dense_bookkeep_batch_kernel(int N, const DenseStep* __restrict__ steps,
+                                                                   const int* __restrict__ pperm,
+                                                                   const int* __restrict__ ppiv,
+                                                                   const double* __restrict__ pd,
+                                                                   const int* __restrict__ pnelim, int* gperm,
+                                                                   int* gpiv, double* gd) {
+  __shared__ int old[CTP_MAX_P];
+  const int sys = blockIdx.x;
+  const DenseStep st = steps[sys];
+  if (!st.active) return;
+  const int* perm_p = pperm + (size_t)sys * CTP_MAX_P;
+  const int* piv_p = ppiv + (size_t)sys * CTP_MAX_P;
+  const double* d_p = pd + (size_t)sys * 2 * CTP_MAX_P;
+  int* gp = gperm + (size_t)sys * N;
+  const int k0 = st.k0, pe = st.pe;
+  const int ne = min(max(pnelim[st.slot], 0), pe);
+  for (int q = threadIdx.x; q < pe; q += blockDim.x) old[q] = gp[k0 + q];
+  __syncthreads();
+  for (int q = threadIdx.x; q < pe; q += blockDim.x) gp[k0 + q] = old[perm_p[q]];
+  for (int q = threadIdx.x; q < ne; q += blockDim.x) {
+    gpiv[(size_t)sys * N + k0 + q] = piv_p[q];
+    gd[(size_t)sys * 2 * N + 2 * (k0 + q)] = d_p[2 * q];
+    gd[(size_t)sys * 2 * N + 2 * (k0 + q) + 1] = d_p[2 * q + 1];
+  }
+}
+
+// gperm[i] = i mod N over count systems of order N
+__global__ void dense_iota_kernel(int* gperm, int N, long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < total) gperm[i] = (int)(i % N);
 }
 
 // FP32 working copy of the lower triangle (columns j, rows j..N-1).
@@ -115,9 +171,11 @@ CTP_DEV double l_entry(const double* a, int lda, const int* piv, int i, int k) {
 
 // U(k, i) = L(i, k) for i > k, stored at row k, column i (upper triangle).
 __global__ __launch_bounds__(256) void dense_mirror_kernel(double* a, int lda, const int* __restrict__ piv,
-                                                           int N) {
+                                                           int N, DZ z) {
   // 32 x 32 tiles of the strictly lower triangle, transposed through LDS
   __shared__ double t[32][33];
+  a += blockIdx.z * z.a;
+  piv += blockIdx.z * z.v;
   const int bi = blockIdx.x, bk = blockIdx.y;   // tile row (i), tile column (k)
   if (bi < bk) return;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows of threads
@@ -142,8 +200,12 @@ constexpr int LINV_LDS = DB * (DB + 1) * (int)sizeof(double);
 
 __global__ __launch_bounds__(DB) void dense_linv_kernel(const double* __restrict__ a, int lda,
                                                         const int* __restrict__ piv, int N,
-                                                        double* __restrict__ linv, double* __restrict__ linvt) {
+                                                        double* __restrict__ linv, double* __restrict__ linvt, DZ z) {
   double (*X)[DB + 1] = reinterpret_cast<double (*)[DB + 1]>(dn_dyn);
+  a += blockIdx.z * z.a;
+  piv += blockIdx.z * z.v;
+  linv += blockIdx.z * z.w;
+  linvt += blockIdx.z * z.w;
   const int b = blockIdx.x;
   const int c0 = b * DB;
   const int nb = min(DB, N - c0);
@@ -172,7 +234,10 @@ __global__ __launch_bounds__(DB) void dense_linv_kernel(const double* __restrict
 
 // y (N x nrhs, ldy) <- P b
 __global__ void dense_gather_kernel(const double* __restrict__ b, int ldb, const int* __restrict__ perm,
-                                    double* __restrict__ y, int ldy, int N, int nrhs) {
+                                    double* __restrict__ y, int ldy, int N, int nrhs, DZ z) {
+  b += blockIdx.z * z.b;
+  perm += blockIdx.z * z.v;
+  y += blockIdx.z * z.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (i < N && c < nrhs) y[(size_t)c * ldy + i] = b[(size_t)c * ldb + perm[i]];
@@ -180,7 +245,10 @@ __global__ void dense_gather_kernel(const double* __restrict__ b, int ldb, const
 
 // x <- P^T y
 __global__ void dense_scatter_kernel(const double* __restrict__ y, int ldy, const int* __restrict__ perm,
-                                     double* __restrict__ x, int ldx, int N, int nrhs) {
+                                     double* __restrict__ x, int ldx, int N, int nrhs, DZ z) {
+  y += blockIdx.z * z.y;
+  perm += blockIdx.z * z.v;
+  x += blockIdx.z * z.b;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (i < N && c < nrhs) x[(size_t)c * ldx + perm[i]] = y[(size_t)c * ldy + i];
@@ -188,7 +256,10 @@ __global__ void dense_scatter_kernel(const double* __restrict__ y, int ldy, cons
 
 // z <- D^-1 y (1x1 and 2x2 blocks; a zero pivot gives 0)
 __global__ void dense_dsolve_kernel(const int* __restrict__ piv, const double* __restrict__ d,
-                                    double* __restrict__ y, int ldy, int N, int nrhs) {
+                                    double* __restrict__ y, int ldy, int N, int nrhs, DZ z) {
+  piv += blockIdx.z * z.v;
+  d += blockIdx.z * z.d;
+  y += blockIdx.z * z.y;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (i >= N || c >= nrhs) return;
@@ -215,9 +286,12 @@ constexpr int SW_MAXRHS = 16;
 // One block step of a sweep, on the FP64 matrix cores.  The diagonal
 // block's inverse M (column-major DB x DB, applied as t = M v_blk); rows of
 // the update: the DB-row chunks listed by the grid (workgroup 0 writes t
-// back into v_blk, workgroup q >= 1 updates chunk rlo + (q-1)*DB of v with
-// the off-diagonal block of F, whose column k of the block sits at
-// F + (c0 + k) * ldf).  Both products of the step
+// into the block rows of the second vector vo, workgroup q >= 1 updates
+// chunk rlo + (q-1)*DB of v with the off-diagonal block of F, whose column
+// k of the block sits at F + (c0 + k) * ldf).  Every workgroup reads v_blk
+// and none writes it, so the result does not depend on which workgroups
+// of the launch run at the same time; a sweep reads v and leaves its
+// solution, block by block, in vo.  Both products of the step
 // -- t = M v_blk (128 x 128 by 128 x nrhs) and the update of a 128-row
 // chunk by F(chunk, blk) t -- are v_mfma_f64_16x16x4 products with the
 // right-hand sides as the 16 columns of B (nrhs <= 16, the rest zero).
@@ -227,8 +301,14 @@ typedef double d4w __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void dense_sweep_mfma_kernel(const double* __restrict__ F, int ldf,
                                                                 const double* __restrict__ M, int c0, int nb,
                                                                 int rlo, int rhi, const int* __restrict__ piv,
-                                                                double* __restrict__ v, int ldv, int nrhs) {
+                                                                double* __restrict__ v, double* __restrict__ vo,
+                                                                int ldv, int nrhs, DZ z) {
   __shared__ double vb[DB][17];   // v_blk, then t, by (k, rhs)
+  F += blockIdx.z * z.a;
+  M += blockIdx.z * z.w;
+  if (piv) piv += blockIdx.z * z.v;
+  v += blockIdx.z * z.y;
+  vo += blockIdx.z * z.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int fr = lane & 15, fk = lane >> 4;
   for (int q = tid; q < DB * 16; q += 256) {
@@ -260,7 +340,7 @@ __global__ __launch_bounds__(256) void dense_sweep_mfma_kernel(const double* __r
   if (blockIdx.x == 0) {
     for (int q = tid; q < DB * 16; q += 256) {
       const int k = q % DB, c = q / DB;
-      if (k < nb && c < nrhs) v[(size_t)c * ldv + c0 + k] = vb[k][c];
+      if (k < nb && c < nrhs) vo[(size_t)c * ldv + c0 + k] = vb[k][c];
     }
     return;
   }
@@ -398,8 +478,11 @@ __global__ void dense_axpy_kernel(double* __restrict__ x, int ldx, const double*
 // so Abar is exactly symmetric whatever the compiler contracts.
 __global__ __launch_bounds__(256) void dense_sym_outer_kernel(const double* __restrict__ bbar, int ldb,
                                                               const double* __restrict__ x, int ldx, int N,
-                                                              int nrhs, double* __restrict__ abar, int ldg) {
+                                                              int nrhs, double* __restrict__ abar, int ldg, DZ z) {
   __shared__ double bj[SW_MAXRHS], xj[SW_MAXRHS];
+  bbar += blockIdx.z * z.b;
+  x += blockIdx.z * z.x;
+  abar += blockIdx.z * z.g;
   const int j = blockIdx.y;
   if (threadIdx.x < nrhs) {
     bj[threadIdx.x] = bbar[(size_t)threadIdx.x * ldb + j];
@@ -459,11 +542,55 @@ static DenseWork dense_layout(int N, int pw, const ctp_opts* o, int nrhs_max) {
     w.w32_off = off; off = align_up(off + (size_t)w.ld32 * N * sizeof(float), 256);
     w.ops_off = off; off = align_up(off + lowp_ops_bytes(N, pmax), 256);
   }
-  w.y_off = off; off = align_up(off + (size_t)2 * N * (nrhs_max > 0 ? nrhs_max : 1) * sizeof(double), 256);
+  w.y_off = off; off = align_up(off + (size_t)3 * N * (nrhs_max > 0 ? nrhs_max : 1) * sizeof(double), 256);
   w.arow_off = off; off = align_up(off + (size_t)(N > 0 ? N : 1) * sizeof(double), 256);
   w.norms_off = off; off = align_up(off + (1 + 3 * SW_MAXRHS) * sizeof(double), 256);
   w.total = off;
   (void)pw;
+  return w;
+}
+
+size_t batch_header_bytes(int count);
+
+// Workspace of a batch of systems: one block per system (the inverses of
+// the diagonal blocks of L and their transposes, the solve vectors for up
+// to SW_MAXRHS right-hand sides), the panel outputs of every system, the
+// step descriptors, two node arrays (panels with rows below them, last
+// panels) and the area of the batched supernode calls, sized for nodes of
+// up to (2N, CTP_MAX_P) like the single-system driver.
+struct BatchedDenseWork {
+  size_t sys_bytes = 0;                             // one system's block
+  size_t linv_off = 0, linvt_off = 0, y_off = 0;    // inside a system's block
+  size_t sys_off = 0;
+  size_t pperm_off = 0, ppiv_off = 0, pd_off = 0, pnelim_off = 0, pstatus_off = 0;
+  size_t steps_off = 0, nodes_off = 0;
+  size_t batch_off = 0, batch_bytes = 0;
+  size_t total = 0;
+};
+
+static BatchedDenseWork dense_batched_layout(int count, int N, const ctp_opts* o) {
+  BatchedDenseWork w;
+  const size_t nbk = (size_t)dense_nblocks(N);
+  const size_t c = (size_t)(count > 0 ? count : 1);
+  size_t off = 0;
+  w.linv_off = off; off = align_up(off + nbk * DB * DB * sizeof(double), 256);
+  w.linvt_off = off; off = align_up(off + nbk * DB * DB * sizeof(double), 256);
+  w.y_off = off; off = align_up(off + (size_t)2 * (N > 0 ? N : 1) * SW_MAXRHS * sizeof(double), 256);
+  w.sys_bytes = off;
+  size_t t = 0;
+  w.sys_off = t; t = align_up(t + c * w.sys_bytes, 256);
+  w.pperm_off = t; t = align_up(t + c * CTP_MAX_P * sizeof(int), 256);
+  w.ppiv_off = t; t = align_up(t + c * CTP_MAX_P * sizeof(int), 256);
+  w.pd_off = t; t = align_up(t + c * 2 * CTP_MAX_P * sizeof(double), 256);
+  w.pnelim_off = t; t = align_up(t + 2 * c * sizeof(int), 256);
+  w.pstatus_off = t; t = align_up(t + 2 * c * sizeof(int), 256);
+  w.steps_off = t; t = align_up(t + c * sizeof(DenseStep), 256);
+  w.nodes_off = t; t = align_up(t + 2 * c * sizeof(ctp_node), 256);
+  const int pmax = CTP_MAX_P < N ? CTP_MAX_P : (N > 0 ? N : 1);
+  const Workspace ws = workspace_layout(2 * (N > 0 ? N : 1), pmax, o->method);
+  w.batch_bytes = batch_header_bytes((int)c) + c * align_up(ws.total, 256);
+  w.batch_off = t; t = align_up(t + w.batch_bytes, 256);
+  w.total = t;
   return w;
 }
 
@@ -511,7 +638,7 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
   float* w32 = reinterpret_cast<float*>(base + L.w32_off);
   const bool lowp = opts->prec != 0;
 
-  dense_iota_kernel<<<(N + 255) / 256, 256, 0, stream>>>(perm, N);
+  dense_iota_kernel<<<(N + 255) / 256, 256, 0, stream>>>(perm, N, N);
   if (lowp) dense_to_f32_kernel<<<dim3(4, N), 256, 0, stream>>>(a, lda, w32, L.ld32, N);
 
   ctp_opts po = *opts;
@@ -558,12 +685,12 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
   // solve preparation
   {
     dim3 mg(dense_nblocks(N) * (DB / 32), dense_nblocks(N) * (DB / 32));
-    dense_mirror_kernel<<<mg, 256, 0, stream>>>(a, lda, piv, N);
+    dense_mirror_kernel<<<mg, 256, 0, stream>>>(a, lda, piv, N, DZ{});
     hipFuncSetAttribute(reinterpret_cast<const void*>(dense_linv_kernel),
                         hipFuncAttributeMaxDynamicSharedMemorySize, LINV_LDS);
     dense_linv_kernel<<<dense_nblocks(N), DB, LINV_LDS, stream>>>(a, lda, piv, N,
                                                           reinterpret_cast<double*>(base + L.linv_off),
-                                                          reinterpret_cast<double*>(base + L.linvt_off));
+                                                          reinterpret_cast<double*>(base + L.linvt_off), DZ{});
   }
   int* st_out = status;
   hipMemcpyAsync(st_out, &acc_status, sizeof(int), hipMemcpyHostToDevice, stream);
@@ -589,29 +716,32 @@ int ctp_ldlt_solve(int N, int nrhs, const double* a, int lda, const int* perm, c
   if (!work || lwork < L.total) return -13;
   if (N == 0 || nrhs == 0) return 0;
   unsigned char* base = static_cast<unsigned char*>(work);
-  double* y = reinterpret_cast<double*>(base + L.y_off);
+  // two solve vectors: the forward sweep reads y1 and leaves L^-1 y in y2,
+  // the backward sweep reads y2 and leaves the solution in y1
+  double* y1 = reinterpret_cast<double*>(base + L.y_off);
+  double* y2 = y1 + (size_t)N * nrhs;
   const int ldy = N;
   const double* linv = reinterpret_cast<const double*>(base + L.linv_off);
   const double* linvt = reinterpret_cast<const double*>(base + L.linvt_off);
   const dim3 eg((N + 255) / 256, nrhs);
-  dense_gather_kernel<<<eg, 256, 0, stream>>>(b, ldb, perm, y, ldy, N, nrhs);
+  dense_gather_kernel<<<eg, 256, 0, stream>>>(b, ldb, perm, y1, ldy, N, nrhs, DZ{});
   const int nbk = dense_nblocks(N);
   for (int j = 0; j < nbk; ++j) {          // forward: L y' = y
     const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
     const int rlo = c0 + nb, rhi = N;
     const int chunks = (rhi - rlo + DB - 1) / DB;
     dense_sweep_mfma_kernel<<<1 + chunks, 256, 0, stream>>>(a, lda, linv + (size_t)j * DB * DB, c0, nb, rlo, rhi,
-                                                            piv, y, ldy, nrhs);
+                                                            piv, y1, y2, ldy, nrhs, DZ{});
   }
-  dense_dsolve_kernel<<<eg, 256, 0, stream>>>(piv, d, y, ldy, N, nrhs);
+  dense_dsolve_kernel<<<eg, 256, 0, stream>>>(piv, d, y2, ldy, N, nrhs, DZ{});
   for (int j = nbk - 1; j >= 0; --j) {     // backward: L^T x' = z, L^T in the upper triangle
     const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
     const int rlo = 0, rhi = c0;
     const int chunks = (rhi - rlo + DB - 1) / DB;
     dense_sweep_mfma_kernel<<<1 + chunks, 256, 0, stream>>>(a, lda, linvt + (size_t)j * DB * DB, c0, nb, rlo, rhi,
-                                                            nullptr, y, ldy, nrhs);
+                                                            nullptr, y2, y1, ldy, nrhs, DZ{});
   }
-  dense_scatter_kernel<<<eg, 256, 0, stream>>>(y, ldy, perm, b, ldb, N, nrhs);
+  dense_scatter_kernel<<<eg, 256, 0, stream>>>(y1, ldy, perm, b, ldb, N, nrhs, DZ{});
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
@@ -632,7 +762,7 @@ int ctp_ldlt_refine(int N, int nrhs, const double* a0, int lda0, const double* f
   if (!work || lwork < L.total) return -20;
   if (N == 0) return 0;
   unsigned char* base = static_cast<unsigned char*>(work);
-  double* r = reinterpret_cast<double*>(base + L.y_off) + (size_t)N * nrhs;   // second half of y
+  double* r = reinterpret_cast<double*>(base + L.y_off) + (size_t)2 * N * nrhs;   // after the solve vectors
   double* arow = reinterpret_cast<double*>(base + L.arow_off);
   double* norms = reinterpret_cast<double*>(base + L.norms_off);
   const int nn = 1 + 3 * nrhs;
@@ -684,7 +814,240 @@ int ctp_ldlt_adjoint(int N, int nrhs, const double* a, int lda, const int* perm,
   // bbar = A^-1 xbar (A symmetric: A^-T = A^-1), in place of xbar
   int rc = ctp_ldlt_solve(N, nrhs, a, lda, perm, piv, d, xbar, ldxb, opts, pw, work, lwork, stream);
   if (rc) return rc;
-  dense_sym_outer_kernel<<<dim3((N + 255) / 256, N), 256, 0, stream>>>(xbar, ldxb, x, ldx, N, nrhs, abar, ldg);
+  dense_sym_outer_kernel<<<dim3((N + 255) / 256, N), 256, 0, stream>>>(xbar, ldxb, x, ldx, N, nrhs, abar, ldg, DZ{});
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+// ---------------------------------------------------------------------------
+// batches of systems
+// ---------------------------------------------------------------------------
+
+static bool batched_method_ok(const ctp_opts* o) {
+  return o && o->prec == 0 && (o->method == CTP_STRICT || o->method == CTP_RELAXED || o->method == CTP_RESTRICTED);
+}
+
+int ctp_dense_batched_workspace_size(int count, int N, int pw, const ctp_opts* opts, size_t* bytes) {
+  if (count < 0) return -1;
+  if (N < 0) return -2;
+  if (pw < 1 || pw > CTP_MAX_P) return -3;
+  if (!batched_method_ok(opts)) return -4;
+  if (!bytes) return -5;
+  *bytes = dense_batched_layout(count, N, opts).total;
+  return 0;
+}
+
+int ctp_ldlt_dense_batched(int count, int N, int pw, double* a, int lda, long long stride, const ctp_opts* opts,
+                           int* perm, int* piv, double* d, int* status, int* nsteps, void* work, size_t lwork,
+                           hipStream_t stream) {
+  if (count < 0) return -1;
+  if (N < 0) return -2;
+  if (pw < 1 || pw > CTP_MAX_P) return -3;
+  if (!a && count > 0 && N > 0) return -4;
+  if (lda < (N > 1 ? N : 1)) return -5;
+  if (count > 1 && stride < (long long)lda * N) return -6;
+  if (!batched_method_ok(opts)) return -7;
+  if (count > 0 && N > 0 && (!perm || !piv || !d)) return -8;
+  if (count > 0 && !status) return -11;
+  const BatchedDenseWork L = dense_batched_layout(count, N, opts);
+  if (!work || lwork < L.total) return -14;
+  if (nsteps) *nsteps = 0;
+  if (count == 0) return 0;
+  std::vector<int> acc(count, 0);
+  if (N == 0) {
+    if (hipMemcpyAsync(status, acc.data(), count * sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+    return 0;
+  }
+  unsigned char* base = static_cast<unsigned char*>(work);
+  int* pperm = reinterpret_cast<int*>(base + L.pperm_off);
+  int* ppiv = reinterpret_cast<int*>(base + L.ppiv_off);
+  double* pd = reinterpret_cast<double*>(base + L.pd_off);
+  int* pnelim = reinterpret_cast<int*>(base + L.pnelim_off);
+  int* pstatus = reinterpret_cast<int*>(base + L.pstatus_off);
+  DenseStep* dsteps = reinterpret_cast<DenseStep*>(base + L.steps_off);
+  ctp_node* dnodes = reinterpret_cast<ctp_node*>(base + L.nodes_off);
+  void* barea = base + L.batch_off;
+
+  const long long total = (long long)count * N;
+  dense_iota_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>(perm, N, total);
+
+  std::vector<int> k0(count, 0), width(count, pw < N ? pw : N), done(count, 0);
+  std::vector<DenseStep> steps(count);
+  std::vector<ctp_node> nm, nr;
+  std::vector<int> hnel(2 * count), hst(2 * count);
+  ctp_opts om = *opts, orr = *opts;
+  om.flags = (opts->flags & ~(CTP_FLAG_ROOT | CTP_FLAG_S_TILED)) | CTP_FLAG_S_SUBTRACT;
+  orr.flags = (opts->flags & ~(CTP_FLAG_S_SUBTRACT | CTP_FLAG_S_TILED)) | CTP_FLAG_ROOT;
+  int nstep = 0;
+  while (true) {
+    nm.clear();
+    nr.clear();
+    int maxk0 = 0;
+    for (int s = 0; s < count; ++s) {
+      steps[s] = DenseStep{k0[s], width[s], 0, 0};
+      if (done[s]) continue;
+      if (width[s] > CTP_MAX_P) return CTP_ERR_PANEL_TOO_WIDE;
+      const int n = N - k0[s];
+      const bool root = n == width[s];
+      ctp_node c;
+      std::memset(&c, 0, sizeof(c));
+      c.n = n;
+      c.p = width[s];
+      c.lda = lda;
+      c.lds = lda;
+      c.a_off = (long long)s * stride + (long long)k0[s] * lda + k0[s];
+      c.s_off = root ? -1 : (long long)s * stride + (long long)(k0[s] + width[s]) * lda + (k0[s] + width[s]);
+      c.out_off = (long long)s * CTP_MAX_P;
+      steps[s].active = 1;
+      if (root) {
+        steps[s].slot = count + (int)nr.size();
+        nr.push_back(c);
+      } else {
+        steps[s].slot = (int)nm.size();
+        nm.push_back(c);
+      }
+      if (k0[s] > maxk0) maxk0 = k0[s];
+    }
+    if (nm.empty() && nr.empty()) break;
+    // panels with rows below them: Factor + Solve + Form subtracted into the
+    // trailing matrices; last panels: Factor with the root rule
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<ctp_node>& nodes = pass == 0 ? nm : nr;
+      if (nodes.empty()) continue;
+      const ctp_opts* po = pass == 0 ? &om : &orr;
+      ctp_batch_info info;
+      int rc = ctp_batch_plan((int)nodes.size(), nodes.data(), po, &info);
+      if (rc) return rc;
+      if (info.work_bytes > L.batch_bytes) return -14;
+      ctp_node* dn = dnodes + (pass == 0 ? 0 : count);
+      if (hipMemcpyAsync(dn, nodes.data(), nodes.size() * sizeof(ctp_node), hipMemcpyHostToDevice, stream) !=
+          hipSuccess)
+        return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+      rc = ctp_supernode_batched((int)nodes.size(), dn, &info, a, pass == 0 ? a : nullptr, pperm, ppiv, pd,
+                                 pnelim + (pass == 0 ? 0 : count), pstatus + (pass == 0 ? 0 : count), po, barea,
+                                 L.batch_bytes, stream);
+      if (rc) return rc;
+    }
+    if (hipMemcpyAsync(dsteps, steps.data(), count * sizeof(DenseStep), hipMemcpyHostToDevice, stream) != hipSuccess)
+      return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+    if (maxk0 > 0)
+      dense_perm_left_batch_kernel<<<dim3(maxk0, count), 256, 0, stream>>>(a, lda, stride, dsteps, pperm);
+    dense_bookkeep_batch_kernel<<<count, 512, 0, stream>>>(N, dsteps, pperm, ppiv, pd, pnelim, perm, piv, d);
+    if (hipMemcpyAsync(hnel.data(), pnelim, 2 * count * sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(hst.data(), pstatus, 2 * count * sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+    for (int s = 0; s < count; ++s) {
+      if (!steps[s].active) continue;
+      const int ne = hnel[steps[s].slot];
+      acc[s] |= hst[steps[s].slot];
+      const int carried = width[s] - ne;
+      k0[s] += ne;
+      width[s] = N - k0[s] < carried + pw ? N - k0[s] : carried + pw;
+      if (k0[s] >= N) done[s] = 1;
+    }
+    ++nstep;
+  }
+  // solve preparation for every system
+  {
+    DZ z;
+    z.a = stride;
+    z.v = N;
+    z.w = (long long)(L.sys_bytes / sizeof(double));
+    const int nb32 = dense_nblocks(N) * (DB / 32);
+    dense_mirror_kernel<<<dim3(nb32, nb32, count), 256, 0, stream>>>(a, lda, piv, N, z);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(dense_linv_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        LINV_LDS);
+    dense_linv_kernel<<<dim3(dense_nblocks(N), 1, count), DB, LINV_LDS, stream>>>(
+        a, lda, piv, N, reinterpret_cast<double*>(base + L.sys_off + L.linv_off),
+        reinterpret_cast<double*>(base + L.sys_off + L.linvt_off), z);
+  }
+  if (hipMemcpyAsync(status, acc.data(), count * sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+  if (nsteps) *nsteps = nstep;
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int ctp_ldlt_solve_batched(int count, int N, int nrhs, const double* a, int lda, long long stride, const int* perm,
+                           const int* piv, const double* d, double* b, int ldb, long long bstride,
+                           const ctp_opts* opts, int pw, void* work, size_t lwork, hipStream_t stream) {
+  if (count < 0) return -1;
+  if (N < 0) return -2;
+  if (nrhs < 0 || nrhs > SW_MAXRHS) return -3;
+  if (!a && count > 0 && N > 0) return -4;
+  if (lda < (N > 1 ? N : 1)) return -5;
+  if (count > 1 && stride < (long long)lda * N) return -6;
+  if (count > 0 && N > 0 && (!perm || !piv || !d)) return -7;
+  if (!b && count > 0 && N > 0 && nrhs > 0) return -10;
+  if (ldb < (N > 1 ? N : 1)) return -11;
+  if (count > 1 && bstride < (long long)ldb * nrhs) return -12;
+  if (!batched_method_ok(opts)) return -13;
+  if (pw < 1 || pw > CTP_MAX_P) return -14;
+  const BatchedDenseWork L = dense_batched_layout(count, N, opts);
+  if (!work || lwork < L.total) return -16;
+  if (count == 0 || N == 0 || nrhs == 0) return 0;
+  unsigned char* base = static_cast<unsigned char*>(work);
+  double* y1 = reinterpret_cast<double*>(base + L.sys_off + L.y_off);
+  double* y2 = y1 + (size_t)N * nrhs;
+  const double* linv = reinterpret_cast<const double*>(base + L.sys_off + L.linv_off);
+  const double* linvt = reinterpret_cast<const double*>(base + L.sys_off + L.linvt_off);
+  const int ldy = N;
+  DZ z;
+  z.a = stride;
+  z.v = N;
+  z.d = 2LL * N;
+  z.y = (long long)(L.sys_bytes / sizeof(double));
+  z.b = bstride;
+  z.w = z.y;
+  const dim3 eg((N + 255) / 256, nrhs, count);
+  dense_gather_kernel<<<eg, 256, 0, stream>>>(b, ldb, perm, y1, ldy, N, nrhs, z);
+  const int nbk = dense_nblocks(N);
+  for (int j = 0; j < nbk; ++j) {
+    const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
+    const int chunks = (N - (c0 + nb) + DB - 1) / DB;
+    dense_sweep_mfma_kernel<<<dim3(1 + chunks, 1, count), 256, 0, stream>>>(
+        a, lda, linv + (size_t)j * DB * DB, c0, nb, c0 + nb, N, piv, y1, y2, ldy, nrhs, z);
+  }
+  dense_dsolve_kernel<<<eg, 256, 0, stream>>>(piv, d, y2, ldy, N, nrhs, z);
+  for (int j = nbk - 1; j >= 0; --j) {
+    const int c0 = j * DB, nb = N - c0 < DB ? N - c0 : DB;
+    const int chunks = (c0 + DB - 1) / DB;
+    dense_sweep_mfma_kernel<<<dim3(1 + chunks, 1, count), 256, 0, stream>>>(
+        a, lda, linvt + (size_t)j * DB * DB, c0, nb, 0, c0, nullptr, y2, y1, ldy, nrhs, z);
+  }
+  dense_scatter_kernel<<<eg, 256, 0, stream>>>(y1, ldy, perm, b, ldb, N, nrhs, z);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int ctp_ldlt_adjoint_batched(int count, int N, int nrhs, const double* a, int lda, long long stride,
+                             const int* perm, const int* piv, const double* d, const double* x, int ldx,
+                             long long xstride, double* xbar, int ldxb, long long xbstride, double* abar, int ldg,
+                             long long gstride, const ctp_opts* opts, int pw, void* work, size_t lwork,
+                             hipStream_t stream) {
+  if (count < 0) return -1;
+  if (N < 0) return -2;
+  if (nrhs < 0 || nrhs > SW_MAXRHS) return -3;
+  if (count > 0 && N > 0 && nrhs > 0) {
+    if (!x || ldx < (N > 1 ? N : 1) || (count > 1 && xstride < (long long)ldx * nrhs)) return -10;
+    if (!xbar || ldxb < (N > 1 ? N : 1) || (count > 1 && xbstride < (long long)ldxb * nrhs)) return -13;
+    if (!abar || ldg < (N > 1 ? N : 1) || (count > 1 && gstride < (long long)ldg * N)) return -16;
+  }
+  if (count == 0 || N == 0 || nrhs == 0) return 0;
+  // bbar = A^-1 xbar for every system, in place of xbar
+  int rc = ctp_ldlt_solve_batched(count, N, nrhs, a, lda, stride, perm, piv, d, xbar, ldxb, xbstride, opts, pw, work,
+                                  lwork, stream);
+  if (rc) return rc;
+  DZ z;
+  z.b = xbstride;
+  z.x = xstride;
+  z.g = gstride;
+  dense_sym_outer_kernel<<<dim3((N + 255) / 256, N, count), 256, 0, stream>>>(xbar, ldxb, x, ldx, N, nrhs, abar, ldg,
+                                                                              z);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }

@@ -523,15 +523,23 @@ static int launch_schur_queue_var(const BatchNode* nodes, int count, int method,
 }
 
 int launch_schur_batch(int count, const BatchNode* nodes, int method, long long total, int tiled,
-                       unsigned int* counter, int variant, int workgroups, hipStream_t stream) {
+                       int subtract, unsigned int* counter, int variant, int workgroups, hipStream_t stream) {
   if (count <= 0 || total <= 0) return 0;
   queue_reset_kernel<<<1, 1, 0, stream>>>(counter);
   const unsigned grid = (unsigned)std::min<long long>(total, workgroups > 0 ? workgroups : 512);
   int rc;
-  switch (variant) {
-    case 1: rc = launch_schur_queue_var<0>(nodes, count, method, total, tiled, counter, grid, stream); break;
-    case 2: rc = launch_schur_queue_var<1>(nodes, count, method, total, tiled, counter, grid, stream); break;
-    default: rc = launch_schur_queue_var<3>(nodes, count, method, total, tiled, counter, grid, stream); break;
+  if (subtract) {
+    switch (variant) {
+      case 1: rc = launch_schur_queue_var<8>(nodes, count, method, total, 0, counter, grid, stream); break;
+      case 2: rc = launch_schur_queue_var<9>(nodes, count, method, total, 0, counter, grid, stream); break;
+      default: rc = launch_schur_queue_var<11>(nodes, count, method, total, 0, counter, grid, stream); break;
+    }
+  } else {
+    switch (variant) {
+      case 1: rc = launch_schur_queue_var<0>(nodes, count, method, total, tiled, counter, grid, stream); break;
+      case 2: rc = launch_schur_queue_var<1>(nodes, count, method, total, tiled, counter, grid, stream); break;
+      default: rc = launch_schur_queue_var<3>(nodes, count, method, total, tiled, counter, grid, stream); break;
+    }
   }
   if (rc) return rc;
   hipError_t e = hipGetLastError();

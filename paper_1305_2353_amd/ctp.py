@@ -36,7 +36,9 @@ CTP_MAX_P = 512
 EXPORTED = ("ctp_default_opts", "ctp_version", "ctp_workspace_size", "ctp_compress",
             "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode", "ctp_schur",
             "ctp_dense_workspace_size", "ctp_ldlt_dense", "ctp_ldlt_solve", "ctp_ldlt_refine",
-            "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched")
+            "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched",
+            "ctp_dense_batched_workspace_size", "ctp_ldlt_dense_batched", "ctp_ldlt_solve_batched",
+            "ctp_ldlt_adjoint_batched")
 
 
 class CtpOpts(ctypes.Structure):
@@ -71,7 +73,7 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise CtpError(f"{path} is missing: build it with `python -m paper_1305_2353_amd.build`")
     lib = ctypes.CDLL(path)
-    P, I, D, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    P, I, D, SZ, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_longlong
     OPT = ctypes.POINTER(CtpOpts)
     sig = {
         "ctp_default_opts": (None, [OPT]),
@@ -90,6 +92,11 @@ def load(path=LIB_PATH):
         "ctp_ldlt_adjoint": (I, [I, I, P, I, P, P, P, P, I, P, I, P, I, OPT, I, P, SZ, P]),
         "ctp_batch_plan": (I, [I, P, OPT, ctypes.POINTER(CtpBatchInfo)]),
         "ctp_supernode_batched": (I, [I, P, ctypes.POINTER(CtpBatchInfo), P, P, P, P, P, P, P, OPT, P, SZ, P]),
+        "ctp_dense_batched_workspace_size": (I, [I, I, I, OPT, ctypes.POINTER(SZ)]),
+        "ctp_ldlt_dense_batched": (I, [I, I, I, P, I, LL, OPT, P, P, P, P, ctypes.POINTER(I), P, SZ, P]),
+        "ctp_ldlt_solve_batched": (I, [I, I, I, P, I, LL, P, P, P, P, I, LL, OPT, I, P, SZ, P]),
+        "ctp_ldlt_adjoint_batched": (I, [I, I, I, P, I, LL, P, P, P, P, I, LL, P, I, LL, P, I, LL, OPT, I, P,
+                                         SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -308,6 +315,85 @@ def ctp_ldlt_adjoint(a, f, x, xbar, opts, work, abar=None):
     _check(load().ctp_ldlt_adjoint(N, nrhs, _ptr(a), lda, _ptr(f["perm"]), _ptr(f["piv"]), _ptr(f["d"]), _ptr(x),
                                    ldx, _ptr(xbar), ldxb, _ptr(abar), ldg, ctypes.byref(opts), f["pw"], _ptr(work),
                                    work.numel(), _stream()), "ctp_ldlt_adjoint")
+    return xbar, abar
+
+
+# ---------------------------------------------------------------------------
+# batches of dense systems
+# ---------------------------------------------------------------------------
+
+def batch_colmajor(t):
+    """(count, N, M) float64 CUDA copy with every system column-major."""
+    return t.detach().to(torch.float64).transpose(1, 2).contiguous().transpose(1, 2)
+
+
+def _batch_args(t, what):
+    if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 3:
+        raise CtpError(f"{what} must be a 3-D float64 CUDA tensor (count, rows, cols)")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise CtpError(f"{what}: every system must be column-major (stride(1) == 1)")
+    count, n, m = t.shape
+    ld = t.stride(2) if m > 1 else max(n, 1)
+    return count, n, m, max(ld, 1), t.stride(0)
+
+
+def ctp_dense_batched_workspace_size(count, N, pw, opts):
+    out = ctypes.c_size_t(0)
+    _check(load().ctp_dense_batched_workspace_size(count, N, pw, ctypes.byref(opts), ctypes.byref(out)),
+           "ctp_dense_batched_workspace_size")
+    return out.value
+
+
+def dense_batched_workspace(count, N, pw, opts, device="cuda"):
+    return torch.empty(max(ctp_dense_batched_workspace_size(count, N, pw, opts), 1), dtype=torch.uint8,
+                       device=device)
+
+
+def ctp_ldlt_dense_batched(a, pw, opts, work):
+    """P A P^T = L D L^T in place for every system of a (count, N, N), each
+    column-major (lower triangles read).  Returns perm, piv (count, N), d
+    (count, 2N), status (count,) on the device and the number of steps."""
+    count, N, M, lda, stride = _batch_args(a, "a")
+    if N != M:
+        raise CtpError("square systems expected")
+    dev = a.device
+    perm = torch.empty((count, max(N, 1)), dtype=torch.int32, device=dev)
+    piv = torch.empty((count, max(N, 1)), dtype=torch.int32, device=dev)
+    d = torch.zeros((count, max(2 * N, 1)), dtype=torch.float64, device=dev)
+    status = torch.zeros(max(count, 1), dtype=torch.int32, device=dev)
+    nsteps = ctypes.c_int(0)
+    _check(load().ctp_ldlt_dense_batched(count, N, pw, _ptr(a), lda, stride, ctypes.byref(opts), _ptr(perm),
+                                         _ptr(piv), _ptr(d), _ptr(status), ctypes.byref(nsteps), _ptr(work),
+                                         work.numel(), _stream()), "ctp_ldlt_dense_batched")
+    return {"perm": perm[:, :N], "piv": piv[:, :N], "d": d[:, :2 * N], "status": status[:count],
+            "nsteps": nsteps.value, "pw": pw, "_perm": perm, "_piv": piv, "_d": d}
+
+
+def ctp_ldlt_solve_batched(a, f, b, opts, work):
+    """b <- A^-1 b in place for every system (b: (count, N, nrhs), each
+    column-major)."""
+    count, N, _, lda, stride = _batch_args(a, "a")
+    cb, nb, nrhs, ldb, bstride = _batch_args(b, "b")
+    assert cb == count and nb == N
+    _check(load().ctp_ldlt_solve_batched(count, N, nrhs, _ptr(a), lda, stride, _ptr(f["_perm"]), _ptr(f["_piv"]),
+                                         _ptr(f["_d"]), _ptr(b), ldb, bstride, ctypes.byref(opts), f["pw"],
+                                         _ptr(work), work.numel(), _stream()), "ctp_ldlt_solve_batched")
+    return b
+
+
+def ctp_ldlt_adjoint_batched(a, f, x, xbar, opts, work, abar=None):
+    """For every system: bbar = A^-1 xbar (in place of xbar) and Abar =
+    -sym(bbar x^T), returned as (count, N, N) column-major per system."""
+    count, N, _, lda, stride = _batch_args(a, "a")
+    _, _, nrhs, ldx, xstride = _batch_args(x, "x")
+    _, _, _, ldxb, xbstride = _batch_args(xbar, "xbar")
+    if abar is None:
+        abar = torch.empty((count, N, N), dtype=torch.float64, device=a.device).transpose(1, 2)
+    _, _, _, ldg, gstride = _batch_args(abar, "abar")
+    _check(load().ctp_ldlt_adjoint_batched(count, N, nrhs, _ptr(a), lda, stride, _ptr(f["_perm"]), _ptr(f["_piv"]),
+                                           _ptr(f["_d"]), _ptr(x), ldx, xstride, _ptr(xbar), ldxb, xbstride,
+                                           _ptr(abar), ldg, gstride, ctypes.byref(opts), f["pw"], _ptr(work),
+                                           work.numel(), _stream()), "ctp_ldlt_adjoint_batched")
     return xbar, abar
 
 

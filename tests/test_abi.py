@@ -94,3 +94,26 @@ def test_workspace_size_and_argument_checks(lib):
                               1 << 30, nul) == -2
     assert lib.ctp_ldlt_solve(100, 2, fake, 100, fake, fake, fake, fake, 100, ctypes.byref(o), 32, fake,
                               16, nul) == -13
+    # batches of dense systems: host-side argument checks
+    bsz = ctypes.c_size_t(0)
+    assert lib.ctp_dense_batched_workspace_size(-1, 100, 32, ctypes.byref(o), ctypes.byref(bsz)) == -1
+    assert lib.ctp_dense_batched_workspace_size(4, 100, 0, ctypes.byref(o), ctypes.byref(bsz)) == -3
+    assert lib.ctp_dense_batched_workspace_size(4, 100, 32, ctypes.byref(lowp), ctypes.byref(bsz)) == -4
+    tpp = ctp.ctp_default_opts("tpp")
+    assert lib.ctp_dense_batched_workspace_size(4, 100, 32, ctypes.byref(tpp), ctypes.byref(bsz)) == -4
+    assert lib.ctp_dense_batched_workspace_size(4, 100, 32, ctypes.byref(o), ctypes.byref(bsz)) == 0
+    assert bsz.value > 0
+    assert lib.ctp_ldlt_dense_batched(4, 100, 32, fake, 100, 9999, ctypes.byref(o), fake, fake, fake, fake, None,
+                                      fake, 1 << 40, nul) == -6
+    assert lib.ctp_ldlt_dense_batched(4, 100, 32, fake, 100, 10000, ctypes.byref(lowp), fake, fake, fake, fake,
+                                      None, fake, 1 << 40, nul) == -7
+    assert lib.ctp_ldlt_dense_batched(4, 100, 32, fake, 100, 10000, ctypes.byref(o), fake, fake, fake, fake, None,
+                                      fake, 16, nul) == -14
+    assert lib.ctp_ldlt_solve_batched(4, 100, 17, fake, 100, 10000, fake, fake, fake, fake, 100, 1700,
+                                      ctypes.byref(o), 32, fake, 1 << 40, nul) == -3
+    assert lib.ctp_ldlt_solve_batched(4, 100, 2, fake, 100, 10000, fake, fake, fake, fake, 100, 199,
+                                      ctypes.byref(o), 32, fake, 1 << 40, nul) == -12
+    assert lib.ctp_ldlt_solve_batched(4, 100, 2, fake, 100, 10000, fake, fake, fake, fake, 100, 200,
+                                      ctypes.byref(o), 32, fake, 16, nul) == -16
+    assert lib.ctp_ldlt_adjoint_batched(4, 100, 2, fake, 100, 10000, fake, fake, fake, fake, 100, 200, fake, 100,
+                                        200, fake, 100, 9999, ctypes.byref(o), 32, fake, 1 << 40, nul) == -16

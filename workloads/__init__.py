@@ -20,6 +20,8 @@ construction.  The recipes here are:
   (its own seeded stream, so a different matrix of the same law): the
   N = 16384 case would take minutes of CPU QR.
 * batch of supernodes: n log-uniform, p uniform with p <= n/4.
+* batch of dense systems (dense_indefinite_batch_torch): S independent
+  draws of the dense_indefinite recipe on the device, one batched QR.
 
 Every array is float64, row index first (n x p); the binding stores panels
 column-major on the device.
@@ -131,3 +133,29 @@ def batch_panel_torch(n, p, gen, device="cuda", small_prob=0.01, small_scale=1e-
     A11 = A11 - torch.diag(a) + torch.diag(d)
     A21 = torch.randn((n - p, p), dtype=torch.float64, device=device, generator=gen)
     return torch.cat([A11, A21])
+
+
+def dense_indefinite_batch_torch(S, N, seed=0, lam_lo=1e-2, nrhs=4, device="cuda"):
+    """S systems of dense_indefinite's recipe drawn with torch on `device`
+    (FP64): Z (S, N, N) Gaussian, Q from one batched QR with the signs of
+    diag(R), lam per system half -U[lam_lo, 1] and half U[lam_lo, 1]
+    shuffled, A = Q diag(lam) Q^T symmetrised, B (S, N, nrhs) Gaussian.
+    Returns (A, B), row-major device tensors."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    Z = torch.randn((S, N, N), dtype=torch.float64, device=device, generator=g)
+    Q, R = torch.linalg.qr(Z)
+    del Z
+    Q = Q * torch.sign(torch.diagonal(R, dim1=1, dim2=2)).unsqueeze(1)
+    del R
+    half = N // 2
+    u = torch.rand((S, N), dtype=torch.float64, device=device, generator=g) * (1.0 - lam_lo) + lam_lo
+    lam = torch.cat([-u[:, :half], u[:, half:]], dim=1)
+    idx = torch.argsort(torch.rand((S, N), device=device, generator=g), dim=1)
+    lam = torch.gather(lam, 1, idx)
+    A = torch.bmm(Q * lam.unsqueeze(1), Q.transpose(1, 2).contiguous())
+    del Q
+    A = 0.5 * (A + A.transpose(1, 2))
+    B = torch.randn((S, N, nrhs), dtype=torch.float64, device=device, generator=g)
+    return A, B
