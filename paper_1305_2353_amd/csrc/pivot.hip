@@ -168,8 +168,7 @@ CTP_DEV int colbuf(int p, int rc, int c) { return 2 * NSLOT * p + NSLOT * rc + c
 
 // Lazily updated entry (i, j) of the square: the stored value minus the
 // pending updates of the ns slots of this batch.
-CTP_DEV double lazy_a(const PivotArgs& g, int ns, int i, int j) {
-  double v = CM(g.T, i, j, g.lda);
+CTP_DEV double lazy_a_from(const PivotArgs& g, int ns, int i, int j, double v) {
   const int p = g.p;
   for (int s = 0; s < ns; ++s) {
     if (pv_sh.kind[s] == 1) {
@@ -195,8 +194,7 @@ CTP_DEV double r_mult(const PivotArgs& g, int rc, int s, int i) {
 }
 
 template <bool CACHED>
-CTP_DEV double lazy_r(const PivotArgs& g, int ns, int rc, int i, int j) {
-  double v = CM(g.R, i, j, g.ldr);
+CTP_DEV double lazy_r_from(const PivotArgs& g, int ns, int rc, int i, int j, double v) {
   const int p = g.p;
   for (int s = 0; s < ns; ++s) {
     if (pv_sh.kind[s] == 1) {
@@ -223,6 +221,15 @@ CTP_DEV double lazy_r(const PivotArgs& g, int ns, int rc, int i, int j) {
     }
   }
   return v;
+}
+
+CTP_DEV double lazy_a(const PivotArgs& g, int ns, int i, int j) {
+  return lazy_a_from(g, ns, i, j, CM(g.T, i, j, g.lda));
+}
+
+template <bool CACHED>
+CTP_DEV double lazy_r(const PivotArgs& g, int ns, int rc, int i, int j) {
+  return lazy_r_from<CACHED>(g, ns, rc, i, j, CM(g.R, i, j, g.ldr));
 }
 
 // This thread's rows of R: rows i = tid (mod NT), the cached ones (i < rc)
@@ -261,24 +268,65 @@ CTP_DEV double top2_excluding(const Top2& t, double x) {
 
 CTP_DEV bool pv_better(double va, int ia, double vb, int ib) { return va > vb || (va == vb && ia < ib); }
 
-// This thread's share of column `col` of the uneliminated trapezoid: rows
-// nelim..p-1 of the square except row `col`, then every row of R.  The
-// values of the square's rows and of the cached R rows are kept in the
-// column buffer at `cb`.
+// The first entries a thread reads in a pass, loaded together before any is
+// used, so that one memory latency covers them (the scans below would
+// otherwise wait for them one loop after another): its first row of the
+// square (nelim + tid) and its first row of R (tid, or rc + tid when
+// tid >= rc, as for_r_rows visits them) in column `col`, and, for the
+// partner search, entry (m, nelim + tid).
+struct ScanPre {
+  bool ht, hr;
+  int ir;
+  double xt, xr;
+};
+
 template <int NT>
-CTP_DEV void col_scan(const PivotArgs& g, int ns, int rc, int nelim, int col, int cb, Top2& t) {
-  for (int i = nelim + threadIdx.x; i < g.p; i += NT) {
+CTP_DEV ScanPre scan_preload(const PivotArgs& g, int rc, int nelim, int col) {
+  ScanPre q;
+  const int it = nelim + threadIdx.x;
+  q.ir = (int)threadIdx.x < rc ? (int)threadIdx.x : rc + (int)threadIdx.x;
+  q.ht = it < g.p && it != col;
+  q.hr = q.ir < g.r;
+  q.xt = q.ht ? CM(g.T, it, col, g.lda) : 0.0;
+  q.xr = q.hr ? CM(g.R, q.ir, col, g.ldr) : 0.0;
+  return q;
+}
+
+// This thread's share of column `col` of the uneliminated trapezoid: rows
+// nelim..p-1 of the square except row `col`, then every row of R, in the
+// order of the plain loops (square rows nelim + tid + k NT; cached R rows
+// tid + k NT, then rc + tid + k NT).  The values of the square's rows and
+// of the cached R rows are kept in the column buffer at `cb`.
+template <int NT>
+CTP_DEV void col_scan(const PivotArgs& g, int ns, int rc, int nelim, int col, int cb, const ScanPre& q, Top2& t) {
+  const int it = nelim + threadIdx.x;
+  if (q.ht) {
+    const double x = lazy_a_from(g, ns, it, col, q.xt);
+    pv_dyn[cb + it] = x;
+    top2_insert(t, fabs(x));
+  }
+  for (int i = it + NT; i < g.p; i += NT) {
     if (i == col) continue;
     const double x = lazy_a(g, ns, i, col);
     pv_dyn[cb + i] = x;
     top2_insert(t, fabs(x));
   }
-  for (int i = threadIdx.x; i < rc; i += NT) {
-    const double x = lazy_r<true>(g, ns, rc, i, col);
-    pv_dyn[cb + g.p + i] = x;
-    top2_insert(t, fabs(x));
+  if ((int)threadIdx.x < rc) {
+    if (q.hr) {
+      const double x = lazy_r_from<true>(g, ns, rc, q.ir, col, q.xr);
+      pv_dyn[cb + g.p + q.ir] = x;
+      top2_insert(t, fabs(x));
+    }
+    for (int i = q.ir + NT; i < rc; i += NT) {
+      const double x = lazy_r<true>(g, ns, rc, i, col);
+      pv_dyn[cb + g.p + i] = x;
+      top2_insert(t, fabs(x));
+    }
+    for (int i = rc + threadIdx.x; i < g.r; i += NT) top2_insert(t, fabs(lazy_r<false>(g, ns, rc, i, col)));
+  } else {
+    if (q.hr) top2_insert(t, fabs(lazy_r_from<false>(g, ns, rc, q.ir, col, q.xr)));
+    for (int i = q.ir + NT; i < g.r; i += NT) top2_insert(t, fabs(lazy_r<false>(g, ns, rc, i, col)));
   }
-  for (int i = rc + threadIdx.x; i < g.r; i += NT) top2_insert(t, fabs(lazy_r<false>(g, ns, rc, i, col)));
 }
 
 // Workgroup reduction of a column's two largest (and, with ARG, of the
@@ -501,19 +549,23 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
     } else {
       // pass A: column m (rows other than m) into colA with its largest two,
       // the partner search along row m, the diagonal entry (thread 0)
+      const ScanPre qa = scan_preload<NT>(g, rc, nelim, m);
+      const int jp = nelim + threadIdx.x;
+      const double xp = jp < m ? CM(g.T, m, jp, g.lda) : 0.0;
+      const double xd = threadIdx.x == 0 ? CM(g.T, m, m, g.lda) : 0.0;
       Top2 cm = top2_empty();
-      col_scan<NT>(g, ns, rc, nelim, m, cA, cm);
+      col_scan<NT>(g, ns, rc, nelim, m, cA, qa, cm);
       double rv = -1.0;
       int ri = 0x7fffffff;
-      for (int j = nelim + threadIdx.x; j < m; j += NT) {
-        double x = fabs(lazy_a(g, ns, m, j));
+      for (int j = jp; j < m; j += NT) {
+        double x = fabs(j == jp ? lazy_a_from(g, ns, m, j, xp) : lazy_a(g, ns, m, j));
         if (x != x) x = -0.5;   // NaN: loses to any number, keeps t a valid index
         if (x > rv) {
           rv = x;
           ri = j;
         }
       }
-      if (threadIdx.x == 0) pv_sh.sc[slot][0] = lazy_a(g, ns, m, m);
+      if (threadIdx.x == 0) pv_sh.sc[slot][0] = lazy_a_from(g, ns, m, m, xd);
       reduce_pass<NT, true>(cm, rv, ri, slot);
       const double amm = pv_sh.sc[slot][0];
       slot ^= 1;
@@ -527,10 +579,12 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
         // pass B: column t (rows other than t) into colB with its largest
         // two; a_tt (thread 0), a_mt (the owner of row m) and a_tm (read
         // back from colA by thread 0) travel with the reduction
+        const ScanPre qb = scan_preload<NT>(g, rc, nelim, t);
+        const double xtt = threadIdx.x == 0 ? CM(g.T, t, t, g.lda) : 0.0;
         Top2 ct = top2_empty();
-        col_scan<NT>(g, ns, rc, nelim, t, cB, ct);
+        col_scan<NT>(g, ns, rc, nelim, t, cB, qb, ct);
         if (threadIdx.x == 0) {
-          pv_sh.sc[slot][0] = lazy_a(g, ns, t, t);
+          pv_sh.sc[slot][0] = lazy_a_from(g, ns, t, t, xtt);
           pv_sh.sc[slot][2] = pv_dyn[cA + t];
         }
         if (threadIdx.x == (m - nelim) % NT) pv_sh.sc[slot][1] = pv_dyn[cB + m];
@@ -891,12 +945,16 @@ __global__ __launch_bounds__(NT) void pivot_factor_batch_kernel(const PivotArgs*
   pivot_factor_wg_body<NT>(g);
 }
 
-// Workgroup size of the search: enough threads for one entry of a column
-// per thread, at least 256 (the apply works on tiles of 256 threads).
+// Workgroup size of the search.  The loop is a chain of short scans, each
+// ended by a workgroup reduction whose cost grows with the number of waves,
+// so when every row of R is cached the search runs with 512 threads (256
+// for at most 256 rows), a few rows per thread; with R rows beyond the
+// cached ones (TPP on a tall panel) the scans stream from memory and get
+// 1024 threads.  The apply works on tiles of 256 threads.
 inline int pivot_threads(int p, int r) {
   const int rc = pivot_rcache(p);
-  const int rows = p + (r < rc ? r : rc);
-  return rows <= 256 ? 256 : rows <= 512 ? 512 : 1024;
+  if (r > rc) return 1024;
+  return p + r <= 256 ? 256 : 512;
 }
 
 template <typename K>
