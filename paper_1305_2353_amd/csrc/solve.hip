@@ -100,21 +100,46 @@ CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, cons
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = w[(size_t)jcc * ldw + rows[q]];
 
-    // X_b -= W_{<b} L_{b,<b}^T over the eliminated columns k < min(j0, nelim)
+    // X_b -= W_{<b} L_{b,<b}^T over the eliminated columns k < min(j0, nelim):
+    // 16 columns of k per step on four independent accumulators (the MFMAs
+    // of a step do not wait for each other), the next step's fragments
+    // loaded while the current step's products run.
     const int kend = min(j0, nelim);
     const int bj = min(j0 + fr, p - 1);      // B operand: row j0+fr of L
-    for (int k0 = 0; k0 < kend; k0 += 4) {
-      const int k = k0 + fk;
+    auto frag = [&](int k, double& af, double& bf) {
       const bool kv = k < kend;
       const int kc = kv ? k : 0;
-      double af = w[(size_t)kc * ldw + arow];
-      double bf = CM(a, bj, kc, lda);
+      af = w[(size_t)kc * ldw + arow];
+      bf = CM(a, bj, kc, lda);
       // L(j0, j0-1) is the in-block entry of a 2x2 pivot straddling the
       // block boundary: it holds D, not L.
       const bool straddle = (j0 + fr == k + 1) && piv_s[kc] == PIV_2X2_FIRST;
       af = kv ? -af : 0.0;
       bf = (kv && !straddle && j0 + fr < p) ? bf : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
+    };
+    if (kend > 0) {
+      d4s part[4];
+      part[0] = acc;
+#pragma unroll
+      for (int u = 1; u < 4; ++u) part[u] = d4s{0.0, 0.0, 0.0, 0.0};
+      double an[4], bn[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) frag(4 * u + fk, an[u], bn[u]);
+      for (int k0 = 0; k0 < kend; k0 += 16) {
+        double ac[4], bc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ac[u] = an[u];
+          bc[u] = bn[u];
+        }
+        if (k0 + 16 < kend) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) frag(k0 + 16 + 4 * u + fk, an[u], bn[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], bc[u], part[u], 0, 0, 0);
+      }
+      acc = (part[0] + part[1]) + (part[2] + part[3]);
     }
 
     // forward substitution inside the block
