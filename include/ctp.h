@@ -113,9 +113,13 @@ typedef struct ctp_opts {
                       1 = FP32 matrix cores, 2 = BF16 matrix cores (FP32
                       accumulation, FP32 trailing matrix); the supernode
                       entry points always compute in FP64 */
-  int tile;        /* Form kernel schedule variant: -1 or 0 = default; with a stored W
-                      1 = no LDS padding, 2 = no padding + mid-chunk staging;
-                      with work = NULL 1 = two rows per staging thread */
+  int tile;        /* Form kernel schedule variant: -1 or 0 = default (with a stored W:
+                      next chunk staged mid-chunk, staging rows split so LDS
+                      stores are contiguous); with a stored W 1 = staging at the
+                      end of the chunk, 2 = mid-chunk staging, 3 = mid-chunk +
+                      padded LDS rows, 4 = 3 + split staging rows (all give the
+                      same bits); with work = NULL 1 = two rows per staging
+                      thread */
   unsigned flags;  /* CTP_FLAG_* bits, default 0 */
 } ctp_opts;
 

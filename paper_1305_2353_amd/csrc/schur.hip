@@ -220,13 +220,16 @@ struct SchurWArgs {
 // thread's 4 rows come in as two 16-byte loads; otherwise 4 clamped loads.
 // VAR selects the schedule: bit 0 writes the next chunk into LDS after
 // three of the four k steps (so a chunk ends with the barrier alone), bit 1
-// pads the LDS rows by 8 doubles.  The default is both (VAR 3), the fastest
-// measured; a second register stage (loads two chunks ahead) spills.  Bit 3
-// subtracts the product from the output instead of storing it (the trailing
-// update of a right-looking factorization).
+// pads the LDS rows by 8 doubles (bit 2: by 16), bit 4 splits a thread's
+// staging rows into two pairs 64 rows apart so that the lanes' 16-byte LDS
+// stores are contiguous.  The default is bits 0 and 4 (VAR 17), the fastest
+// measured (padding does not pay once the stores are contiguous); a second
+// register stage (loads two chunks ahead) spills.  Bit 3 subtracts the
+// product from the output instead of storing it (the trailing update of a
+// right-looking factorization).  Every variant gives the same bits.
 template <int VAR>
 struct SchurWShape {
-  static constexpr int LW = (VAR & 2) ? SC_BM + 8 : SC_BM;   // LDS row stride (doubles)
+  static constexpr int LW = (VAR & 4) ? SC_BM + 16 : (VAR & 2) ? SC_BM + 8 : SC_BM;   // LDS row stride (doubles)
   static constexpr int LDS_BYTES = 2 * 2 * 16 * LW * 8;       // two buffers, two operands
 };
 
@@ -247,14 +250,22 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int ii = (tid % TPK) * RPT;
+  // staging rows of this thread: 4 consecutive rows, or (VAR & 16) the
+  // row pairs 2l, 2l+1 and 64+2l, 64+2l+1, l = tid % 32, so that the lanes'
+  // 16-byte LDS stores are contiguous
+  constexpr bool SPLIT = (VAR & 16) != 0;
+  const int ii = SPLIT ? (tid % TPK) * 2 : (tid % TPK) * RPT;
+  const int ii2 = SPLIT ? ii + SC_BM / 2 : ii + 2;
   const int kq = tid / TPK;
   const int ga = i0 + ii, gb = j0 + ii;
+  const int ga2 = i0 + ii2, gb2 = j0 + ii2;
   int rowa[RPT], rowb[RPT];
 #pragma unroll
   for (int e = 0; e < RPT; ++e) {
-    rowa[e] = VEC ? ga + e : min(ga + e, g.r - 1);
-    rowb[e] = VEC ? gb + e : min(gb + e, g.r - 1);
+    const int oa = e < 2 ? ga + e : ga2 + (e - 2);
+    const int ob = e < 2 ? gb + e : gb2 + (e - 2);
+    rowa[e] = VEC ? oa : min(oa, g.r - 1);
+    rowb[e] = VEC ? ob : min(ob, g.r - 1);
   }
 
   struct Stage {
@@ -274,9 +285,9 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
       const double* cb = g.w + (size_t)kk * g.ldw;
       if (VEC) {
         const double2 x0 = *reinterpret_cast<const double2*>(ca + ga);
-        const double2 x1 = *reinterpret_cast<const double2*>(ca + ga + 2);
+        const double2 x1 = *reinterpret_cast<const double2*>(ca + ga2);
         const double2 y0 = *reinterpret_cast<const double2*>(cb + gb);
-        const double2 y1 = *reinterpret_cast<const double2*>(cb + gb + 2);
+        const double2 y1 = *reinterpret_cast<const double2*>(cb + gb2);
         ra[h][0] = x0.x; ra[h][1] = x0.y; ra[h][2] = x1.x; ra[h][3] = x1.y;
         rb[h][0] = y0.x; rb[h][1] = y0.y; rb[h][2] = y1.x; rb[h][3] = y1.y;
       } else {
@@ -302,12 +313,12 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
       a1.x = m ? ra[h][2] : 0.0; a1.y = m ? ra[h][3] : 0.0;
       b0.x = m ? rb[h][0] : 0.0; b0.y = m ? rb[h][1] : 0.0;
       b1.x = m ? rb[h][2] : 0.0; b1.y = m ? rb[h][3] : 0.0;
-      double* pa = As + (buf * BK + kq + KSTEP * h) * LW + ii;
-      double* pb = Bs + (buf * BK + kq + KSTEP * h) * LW + ii;
-      *reinterpret_cast<double2*>(pa) = a0;
-      *reinterpret_cast<double2*>(pa + 2) = a1;
-      *reinterpret_cast<double2*>(pb) = b0;
-      *reinterpret_cast<double2*>(pb + 2) = b1;
+      double* pa = As + (buf * BK + kq + KSTEP * h) * LW;
+      double* pb = Bs + (buf * BK + kq + KSTEP * h) * LW;
+      *reinterpret_cast<double2*>(pa + ii) = a0;
+      *reinterpret_cast<double2*>(pa + ii2) = a1;
+      *reinterpret_cast<double2*>(pb + ii) = b0;
+      *reinterpret_cast<double2*>(pb + ii2) = b1;
     }
   };
 
@@ -443,7 +454,9 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
   switch (variant) {
     case 1: rc = launch_schur_w_var<0>(g, vec, grid, stream); break;
     case 2: rc = launch_schur_w_var<1>(g, vec, grid, stream); break;
-    default: rc = launch_schur_w_var<3>(g, vec, grid, stream); break;
+    case 3: rc = launch_schur_w_var<3>(g, vec, grid, stream); break;
+    case 4: rc = launch_schur_w_var<19>(g, vec, grid, stream); break;
+    default: rc = launch_schur_w_var<17>(g, vec, grid, stream); break;
   }
   if (rc) return rc;
   hipError_t e = hipGetLastError();
@@ -532,13 +545,13 @@ int launch_schur_batch(int count, const BatchNode* nodes, int method, long long 
     switch (variant) {
       case 1: rc = launch_schur_queue_var<8>(nodes, count, method, total, 0, counter, grid, stream); break;
       case 2: rc = launch_schur_queue_var<9>(nodes, count, method, total, 0, counter, grid, stream); break;
-      default: rc = launch_schur_queue_var<11>(nodes, count, method, total, 0, counter, grid, stream); break;
+      default: rc = launch_schur_queue_var<25>(nodes, count, method, total, 0, counter, grid, stream); break;
     }
   } else {
     switch (variant) {
       case 1: rc = launch_schur_queue_var<0>(nodes, count, method, total, tiled, counter, grid, stream); break;
       case 2: rc = launch_schur_queue_var<1>(nodes, count, method, total, tiled, counter, grid, stream); break;
-      default: rc = launch_schur_queue_var<3>(nodes, count, method, total, tiled, counter, grid, stream); break;
+      default: rc = launch_schur_queue_var<17>(nodes, count, method, total, tiled, counter, grid, stream); break;
     }
   }
   if (rc) return rc;
@@ -572,7 +585,7 @@ int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, 
   const unsigned grid = g.per_xcd * SC_NXCD;
   const bool vec = ((reinterpret_cast<uintptr_t>(a + p) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&
                    lda % 2 == 0 && ldw % 2 == 0;
-  int rc = launch_schur_w_var<11>(g, vec, grid, stream);
+  int rc = launch_schur_w_var<25>(g, vec, grid, stream);
   if (rc) return rc;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
