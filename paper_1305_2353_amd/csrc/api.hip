@@ -13,7 +13,7 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
                         int root, int one_wg, double u, double small, int* perm, int* piv, double* d,
                         int* nelim, int* status, void* state, double* wbuf, hipStream_t stream);
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                 const double* d, const int* nelim, double* w, int ldw, hipStream_t stream);
+                 const double* d, const int* nelim, double* w, int ldw, double* lc, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream);
@@ -153,7 +153,8 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const
   if (!work || lwork < ws.total) return -11;
   double* w = reinterpret_cast<double*>(static_cast<unsigned char*>(work) + ws.w_off);
   if (opts->method == CTP_TPP) return launch_form_w(n, p, a, lda, piv, d, nelim, w, ws.ldw, stream);
-  return launch_solve(n, p, a, lda, perm, piv, d, nelim, w, ws.ldw, stream);
+  double* lc = reinterpret_cast<double*>(static_cast<unsigned char*>(work) + ws.lc_off);
+  return launch_solve(n, p, a, lda, perm, piv, d, nelim, w, ws.ldw, lc, stream);
 }
 
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,

@@ -56,6 +56,7 @@ struct Workspace {
   size_t wb_off = 0;      // pivot-search batch of pivot-column values
   size_t w_off = 0;       // compressed / restricted: (n-p) x p doubles, solve gather buffer
   int ldw = 1;
+  size_t lc_off = 0;      // solve: compact copy of A11 after the pivot search (p x p, ld p)
   size_t misc_off = 0;    // 64 ints of counters / flags
   size_t total = 0;
   int relaxed_chunks = 0;
@@ -116,6 +117,8 @@ __host__ __device__ inline Workspace workspace_layout(int n, int p, int method) 
     w.ldw = (int)align_up((size_t)r, 32);
     w.w_off = off;
     off = align_up(off + (size_t)w.ldw * p * sizeof(double), 256);
+    w.lc_off = off;
+    off = align_up(off + (size_t)p * p * sizeof(double), 256);
   }
   w.misc_off = off;
   off = align_up(off + 64 * sizeof(int), 256);

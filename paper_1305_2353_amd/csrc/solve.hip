@@ -29,19 +29,26 @@ typedef double d4s __attribute__((ext_vector_type(4)));
 constexpr int SOLVE_THREADS = 256;   // 4 waves, 16 rows each
 constexpr int SOLVE_ROWS = 64;
 
-CTP_DEV void solve_gather_body(int r, const double* __restrict__ a21, int lda, const int* __restrict__ perm,
-                               double* __restrict__ w, int ldw, int j, int chunk) {
-  const double* src = a21 + (size_t)perm[j] * lda;
+// Column j of W = A21 P^T (rows chunk*4096 ..), and with the first chunk
+// column j of A11 into the compact p x p copy lc: the solve's L operand,
+// whose columns are then 8p bytes apart instead of 8 lda bytes (every step
+// of the solve reads four columns of L; at lda = 100000 those sit in four
+// different pages).
+CTP_DEV void solve_gather_body(int r, int p, const double* __restrict__ a, int lda, const int* __restrict__ perm,
+                               double* __restrict__ w, int ldw, double* __restrict__ lc, int j, int chunk) {
+  const double* src = a + p + (size_t)perm[j] * lda;
   double* dst = w + (size_t)j * ldw;
   const int i0 = chunk * 4096;
   const int i1 = min(r, i0 + 4096);
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
+  if (chunk == 0)
+    for (int i = threadIdx.x; i < p; i += blockDim.x) lc[(size_t)j * p + i] = a[(size_t)j * lda + i];
 }
 
-__global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a21,
-                                                         int lda, const int* __restrict__ perm,
-                                                         double* __restrict__ w, int ldw) {
-  solve_gather_body(r, a21, lda, perm, w, ldw, blockIdx.y, blockIdx.x);
+__global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a, int lda,
+                                                         const int* __restrict__ perm, double* __restrict__ w,
+                                                         int ldw, double* __restrict__ lc) {
+  solve_gather_body(r, p, a, lda, perm, w, ldw, lc, blockIdx.y, blockIdx.x);
 }
 
 // 2x2 pivot inverse entries, scaled as in the pivot search.
@@ -59,7 +66,7 @@ __shared__ double slv_d[2 * CTP_MAX_P + 64];
 
 CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
                              const double* __restrict__ d, const int* __restrict__ nelim_p,
-                             double* __restrict__ w, int ldw, int bx) {
+                             double* __restrict__ w, int ldw, const double* __restrict__ lc, int bx) {
   int* piv_s = slv_piv;
   double* d_s = slv_d;
   for (int k = threadIdx.x; k < p + 32; k += SOLVE_THREADS) {
@@ -103,41 +110,63 @@ CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, cons
     // X_b -= W_{<b} L_{b,<b}^T over the eliminated columns k < min(j0, nelim):
     // 16 columns of k per step on four independent accumulators (the MFMAs
     // of a step do not wait for each other), the next step's fragments
-    // loaded while the current step's products run.
+    // loaded while the current step's products run.  Every step but the
+    // last is full and cannot meet the 2x2 pivot that may straddle the
+    // block boundary (k = j0 - 1), so it runs on pointer increments without
+    // masks; the last step takes the masked loads.
     const int kend = min(j0, nelim);
     const int bj = min(j0 + fr, p - 1);      // B operand: row j0+fr of L
-    auto frag = [&](int k, double& af, double& bf) {
-      const bool kv = k < kend;
-      const int kc = kv ? k : 0;
-      af = w[(size_t)kc * ldw + arow];
-      bf = CM(a, bj, kc, lda);
-      // L(j0, j0-1) is the in-block entry of a 2x2 pivot straddling the
-      // block boundary: it holds D, not L.
-      const bool straddle = (j0 + fr == k + 1) && piv_s[kc] == PIV_2X2_FIRST;
-      af = kv ? -af : 0.0;
-      bf = (kv && !straddle && j0 + fr < p) ? bf : 0.0;
-    };
+    const bool brow = j0 + fr < p;
     if (kend > 0) {
+      const int klast = (kend - 1) / 16 * 16;   // first k of the last step
       d4s part[4];
       part[0] = acc;
 #pragma unroll
       for (int u = 1; u < 4; ++u) part[u] = d4s{0.0, 0.0, 0.0, 0.0};
+      const size_t wstep = (size_t)4 * ldw, lstep = (size_t)4 * p;
+      const double* wp = w + (size_t)fk * ldw + arow;   // W(arow, k), k = fk + 4u + k0
+      const double* lp = lc + (size_t)fk * p + bj;      // L(bj, k)
       double an[4], bn[4];
+      if (klast > 0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) frag(4 * u + fk, an[u], bn[u]);
-      for (int k0 = 0; k0 < kend; k0 += 16) {
+        for (int u = 0; u < 4; ++u) {
+          an[u] = -wp[u * wstep];
+          bn[u] = brow ? lp[u * lstep] : 0.0;
+        }
+      }
+      for (int k0 = 0; k0 < klast; k0 += 16) {
         double ac[4], bc[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           ac[u] = an[u];
           bc[u] = bn[u];
         }
-        if (k0 + 16 < kend) {
+        wp += 4 * wstep;
+        lp += 4 * lstep;
+        if (k0 + 16 < klast) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) frag(k0 + 16 + 4 * u + fk, an[u], bn[u]);
+          for (int u = 0; u < 4; ++u) {
+            an[u] = -wp[u * wstep];
+            bn[u] = brow ? lp[u * lstep] : 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], bc[u], part[u], 0, 0, 0);
+      }
+      // last step: k = klast .. kend-1
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = klast + 4 * u + fk;
+        const bool kv = k < kend;
+        const int kc = kv ? k : 0;
+        double af = w[(size_t)kc * ldw + arow];
+        double bf = CM(lc, bj, kc, p);
+        // L(j0, j0-1) is the in-block entry of a 2x2 pivot straddling the
+        // block boundary: it holds D, not L.
+        const bool straddle = (j0 + fr == k + 1) && piv_s[kc] == PIV_2X2_FIRST;
+        af = kv ? -af : 0.0;
+        bf = (kv && !straddle && brow) ? bf : 0.0;
+        part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, part[u], 0, 0, 0);
       }
       acc = (part[0] + part[1]) + (part[2] + part[3]);
     }
@@ -146,7 +175,7 @@ CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, cons
     const int kkend = min(16, nelim - j0);
     for (int kk = 0; kk < kkend; ++kk) {
       const int k = j0 + kk;
-      double lv = CM(a, jcc, k, lda);
+      double lv = CM(lc, jcc, k, p);
       const bool keep = cv && c > kk && !(c == kk + 1 && piv_s[k] == PIV_2X2_FIRST);
       lv = keep ? lv : 0.0;
       if (piv_s[k] == PIV_ZERO && c == kk) {
@@ -212,8 +241,9 @@ CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, cons
 
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
     int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
-    const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw) {
-  solve_mfma_body(r, p, a, lda, piv, d, nelim_p, w, ldw, blockIdx.x);
+    const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw,
+    const double* __restrict__ lc) {
+  solve_mfma_body(r, p, a, lda, piv, d, nelim_p, w, ldw, lc, blockIdx.x);
 }
 
 // Batched: the node is blockIdx.z (gather) / blockIdx.y (solve).
@@ -222,8 +252,8 @@ __global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode
   const int r = nd.n - nd.p;
   if ((int)blockIdx.y >= nd.p || (int)blockIdx.x * 4096 >= r) return;
   const Workspace ws = workspace_layout(nd.n, nd.p, method);
-  solve_gather_body(r, nd.a + nd.p, nd.lda, nd.perm, reinterpret_cast<double*>(nd.work + ws.w_off), ws.ldw,
-                    blockIdx.y, blockIdx.x);
+  solve_gather_body(r, nd.p, nd.a, nd.lda, nd.perm, reinterpret_cast<double*>(nd.work + ws.w_off), ws.ldw,
+                    reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y, blockIdx.x);
 }
 
 __global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_batch_kernel(const BatchNode* __restrict__ nodes,
@@ -233,7 +263,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_batch_kernel(const B
   if ((int)blockIdx.x * SOLVE_ROWS >= r) return;
   const Workspace ws = workspace_layout(nd.n, nd.p, method);
   solve_mfma_body(r, nd.p, nd.a, nd.lda, nd.piv, nd.d, nd.nelim, reinterpret_cast<double*>(nd.work + ws.w_off),
-                  ws.ldw, blockIdx.x);
+                  ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), blockIdx.x);
 }
 
 int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream) {
@@ -286,13 +316,13 @@ int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const 
 }
 
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                 const double* d, const int* nelim, double* w, int ldw, hipStream_t stream) {
+                 const double* d, const int* nelim, double* w, int ldw, double* lc, hipStream_t stream) {
   const int r = n - p;
   if (r <= 0 || p <= 0) return 0;
   dim3 gg((r + 4095) / 4096, p);
-  solve_gather_kernel<<<gg, 256, 0, stream>>>(r, p, a + p, lda, perm, w, ldw);
+  solve_gather_kernel<<<gg, 256, 0, stream>>>(r, p, a, lda, perm, w, ldw, lc);
   solve_mfma_kernel<<<(r + SOLVE_ROWS - 1) / SOLVE_ROWS, SOLVE_THREADS, 0, stream>>>(r, p, a, lda, piv, d,
-                                                                                 nelim, w, ldw);
+                                                                                 nelim, w, ldw, lc);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
