@@ -239,7 +239,7 @@ CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, cons
   }
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_kernel(
+__global__ __launch_bounds__(SOLVE_THREADS, 3) void solve_mfma_kernel(
     int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
     const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw,
     const double* __restrict__ lc) {
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode
                     reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y, blockIdx.x);
 }
 
-__global__ __launch_bounds__(SOLVE_THREADS) void solve_mfma_batch_kernel(const BatchNode* __restrict__ nodes,
+__global__ __launch_bounds__(SOLVE_THREADS, 3) void solve_mfma_batch_kernel(const BatchNode* __restrict__ nodes,
                                                                          int method) {
   const BatchNode& nd = nodes[blockIdx.y];
   const int r = nd.n - nd.p;
