@@ -37,12 +37,12 @@ BLOCK_ROWS = 4096
 
 # HBM bytes per Form launch from two rocprofv3 --pmc runs (FETCH_SIZE scaled by
 # the 1.9997 read factor measured on a plain copy of known size, WRITE_SIZE
-# unscaled): 2.416 GB read + 1.584 GB written on average over the 25 launches
+# unscaled): 2.409 GB read + 1.584 GB written on average over the 25 launches
 # of the n=100000, p=512 step, valid only for the kernel source they were
 # measured on.
 FORM_COUNTERS = {
-    "source_sha256": "f18d303a3da0a99d18242d92ebc9bb935a89643e831970ec9af9d40b78e831d1",
-    "hbm_bytes_per_launch": 3999677343,
+    "source_sha256": "f28fcdbc0b05e4bf4ede0be58c3a6f39f737a2db98617af4af146b046b0ccc36",
+    "hbm_bytes_per_launch": 3993212116,
     "n": 100000, "p": 512,
 }
 
