@@ -192,15 +192,18 @@ __global__ __launch_bounds__(256) void dense_mirror_kernel(double* a, int lda, c
   }
 }
 
-// Inverse of the unit lower diagonal block b (columns b*DB ..): each thread
-// owns one column j of X = L_bb^-1 and runs the forward substitution for
-// it, X(i, j) = -sum_{j <= k < i} L(i, k) X(k, j), the column kept in LDS.
+// Inverse of the unit lower diagonal block b (columns b*DB ..): thread j
+// owns column j of X = L_bb^-1 (kept in LDS) and solves L x = e_j column
+// by column: at step k, column k of L below the diagonal is staged in LDS
+// once for the workgroup and every column j <= k takes x(i) -= L(i, k) x(k)
+// for its rows i > k.
 extern __shared__ double dn_dyn[];
 constexpr int LINV_LDS = DB * (DB + 1) * (int)sizeof(double);
 
 __global__ __launch_bounds__(DB) void dense_linv_kernel(const double* __restrict__ a, int lda,
                                                         const int* __restrict__ piv, int N,
                                                         double* __restrict__ linv, double* __restrict__ linvt, DZ z) {
+  __shared__ double lcol[DB];
   double (*X)[DB + 1] = reinterpret_cast<double (*)[DB + 1]>(dn_dyn);
   a += blockIdx.z * z.a;
   piv += blockIdx.z * z.v;
@@ -210,13 +213,17 @@ __global__ __launch_bounds__(DB) void dense_linv_kernel(const double* __restrict
   const int c0 = b * DB;
   const int nb = min(DB, N - c0);
   const int j = threadIdx.x;
-  for (int i = 0; i < DB; ++i) X[i][j] = 0.0;
-  if (j < nb) {
-    X[j][j] = 1.0;
-    for (int i = j + 1; i < nb; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s = fma(l_entry(a, lda, piv, c0 + i, c0 + k), X[k][j], s);
-      X[i][j] = -s;
+  for (int i = 0; i < DB; ++i) X[i][j] = (i == j && j < nb) ? 1.0 : 0.0;
+  for (int k = 0; k + 1 < nb; ++k) {
+    __syncthreads();   // the previous step's reads of lcol are done
+    {
+      const int i = threadIdx.x;
+      lcol[i] = (i > k && i < nb) ? l_entry(a, lda, piv, c0 + i, c0 + k) : 0.0;
+    }
+    __syncthreads();
+    if (j <= k) {
+      const double xk = X[k][j];
+      for (int i = k + 1; i < nb; ++i) X[i][j] = fma(-lcol[i], xk, X[i][j]);
     }
   }
   __syncthreads();
