@@ -212,7 +212,7 @@ extern __shared__ unsigned char cmp_smem[];
 
 CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, int lda, int nchunks,
                                  const Cand* __restrict__ cand, double* __restrict__ c, int ldc,
-                                 int* __restrict__ crow_out, int* __restrict__ status) {
+                                 int* __restrict__ crow_out, int* __restrict__ status, bool gather) {
   constexpr int K = RELAXED_TOPK;
   Cand* lists = reinterpret_cast<Cand*>(cmp_smem);
   int* chosen = reinterpret_cast<int*>(lists + (size_t)p * K);
@@ -335,14 +335,30 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
   }
   __syncthreads();
 
-  // 3. Gather the chosen signed rows into C (zero rows when none).
-  for (int q = threadIdx.x; q < p * p; q += blockDim.x) {
-    int j = q % p, k = q / p;    // consecutive threads walk down a column of C
-    int row = chosen[j];
-    c[(size_t)k * ldc + j] = row >= 0 ? a21[(size_t)k * lda + row] : 0.0;
+  // 3. Gather the chosen signed rows into C (zero rows when none), here or
+  //    (gather == false) by relaxed_gather_kernel from crow_out.
+  if (gather) {
+    for (int q = threadIdx.x; q < p * p; q += blockDim.x) {
+      int j = q % p, k = q / p;    // consecutive threads walk down a column of C
+      int row = chosen[j];
+      c[(size_t)k * ldc + j] = row >= 0 ? a21[(size_t)k * lda + row] : 0.0;
+    }
   }
   if (crow_out)
     for (int j = threadIdx.x; j < p; j += blockDim.x) crow_out[j] = chosen[j];
+}
+
+// C(j, k) = A21(chosen[j], k) (0 when no row was left): one workgroup per
+// column k and 256 rows of C, so the scattered reads of the chosen rows are
+// spread over the whole GPU instead of queued in one workgroup.
+__global__ __launch_bounds__(256) void relaxed_gather_kernel(int p, const double* __restrict__ a21, int lda,
+                                                           const int* __restrict__ chosen, double* __restrict__ c,
+                                                           int ldc) {
+  const int k = blockIdx.x;
+  for (int j = blockIdx.y * 256 + threadIdx.x; j < p; j += gridDim.y * 256) {
+    const int row = chosen[j];
+    c[(size_t)k * ldc + j] = row >= 0 ? a21[(size_t)k * lda + row] : 0.0;
+  }
 }
 
 __global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, const double* __restrict__ a21,
@@ -351,7 +367,7 @@ __global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, cons
                                                             double* __restrict__ c, int ldc,
                                                             int* __restrict__ crow_out,
                                                             int* __restrict__ status) {
-  relaxed_select_body(r, p, a21, lda, nchunks, cand, c, ldc, crow_out, status);
+  relaxed_select_body(r, p, a21, lda, nchunks, cand, c, ldc, crow_out, status, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,7 +411,9 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
       if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
     }
     if (r > 0) {
-      relaxed_select_kernel<<<1, 1024, lds, stream>>>(r, p, a21, lda, nch, cand, c, ldc, crow, status);
+      int* rows = crow ? crow : reinterpret_cast<int*>(base + ws.crow_off);
+      relaxed_select_kernel<<<1, 1024, lds, stream>>>(r, p, a21, lda, nch, cand, c, ldc, rows, status);
+      relaxed_gather_kernel<<<dim3(p, (p + 255) / 256), 256, 0, stream>>>(p, a21, lda, rows, c, ldc);
     } else {
       size_t cnt = (size_t)ldc * p;
       fill_u64_kernel<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, stream>>>(
@@ -457,7 +475,7 @@ __global__ __launch_bounds__(1024) void relaxed_select_batch_kernel(const BatchN
   int* crow = reinterpret_cast<int*>(nd.work + ws.crow_off);
   if (r > 0) {
     relaxed_select_body(r, nd.p, nd.a + nd.p, nd.lda, nd.nchunks, reinterpret_cast<const Cand*>(nd.work + ws.cand_off),
-                        c, nd.p, crow, nd.status);
+                        c, nd.p, crow, nd.status, true);
   } else {
     for (int q = threadIdx.x; q < nd.p * nd.p; q += blockDim.x) c[q] = 0.0;
     for (int j = threadIdx.x; j < nd.p; j += blockDim.x) crow[j] = -1;
