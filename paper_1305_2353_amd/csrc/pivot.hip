@@ -329,23 +329,72 @@ CTP_DEV void col_scan(const PivotArgs& g, int ns, int rc, int nelim, int col, in
   }
 }
 
+// Cross-lane moves of the reductions.  Within a row of 16 lanes the
+// butterfly uses DPP (quad permutes for lane distance 1 and 2, then the
+// half-row and row mirrors, which pair disjoint groups once the quads, then
+// the half-rows, agree); across rows, LDS permutes; the workgroup result is
+// broadcast with readfirstlane.
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm(1, 0, 3, 2)
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm(2, 3, 0, 1)
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <- 7 - i within each 8 lanes
+constexpr int DPP_MIRROR = 0x140;       // lane i <- 15 - i within each 16 lanes
+
+template <int CTRL>
+CTP_DEV int dpp_int(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+CTP_DEV double dpp_dbl(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)dpp_int<CTRL>((int)(unsigned)(b & 0xffffffffull));
+  const unsigned hi = (unsigned)dpp_int<CTRL>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+CTP_DEV double first_lane_dbl(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffull));
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <bool ARG>
+CTP_DEV void red_merge(Top2& t, double& rv, int& ri, double o1, double o2, double ov, int oi) {
+  top2_merge(t, o1, o2);
+  if (ARG && pv_better(ov, oi, rv, ri)) {
+    rv = ov;
+    ri = oi;
+  }
+}
+
+template <bool ARG, int CTRL>
+CTP_DEV void red_round_dpp(Top2& t, double& rv, int& ri) {
+  const double o1 = dpp_dbl<CTRL>(t.v1), o2 = dpp_dbl<CTRL>(t.v2);
+  const double ov = ARG ? dpp_dbl<CTRL>(rv) : 0.0;
+  const int oi = ARG ? dpp_int<CTRL>(ri) : 0;
+  red_merge<ARG>(t, rv, ri, o1, o2, ov, oi);
+}
+
+template <bool ARG>
+CTP_DEV void red_round_shfl(Top2& t, double& rv, int& ri, int off) {
+  const double o1 = __shfl_xor(t.v1, off, 64), o2 = __shfl_xor(t.v2, off, 64);
+  const double ov = ARG ? __shfl_xor(rv, off, 64) : 0.0;
+  const int oi = ARG ? __shfl_xor(ri, off, 64) : 0;
+  red_merge<ARG>(t, rv, ri, o1, o2, ov, oi);
+}
+
 // Workgroup reduction of a column's two largest (and, with ARG, of the
 // partner search); the caller reads the slot's scalars, then flips the slot.
 template <int NT, bool ARG>
 CTP_DEV void reduce_pass(Top2& t, double& rv, int& ri, int slot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int off = 32; off > 0; off >>= 1) {
-    const double o1 = __shfl_xor(t.v1, off, 64), o2 = __shfl_xor(t.v2, off, 64);
-    top2_merge(t, o1, o2);
-    if (ARG) {
-      const double ov = __shfl_xor(rv, off, 64);
-      const int oi = __shfl_xor(ri, off, 64);
-      if (pv_better(ov, oi, rv, ri)) {
-        rv = ov;
-        ri = oi;
-      }
-    }
-  }
+  red_round_dpp<ARG, DPP_XOR1>(t, rv, ri);
+  red_round_dpp<ARG, DPP_XOR2>(t, rv, ri);
+  red_round_dpp<ARG, DPP_HALF_MIRROR>(t, rv, ri);
+  red_round_dpp<ARG, DPP_MIRROR>(t, rv, ri);
+  red_round_shfl<ARG>(t, rv, ri, 16);
+  red_round_shfl<ARG>(t, rv, ri, 32);
   if (lane == 0) {
     pv_sh.v1[slot][wave] = t.v1;
     pv_sh.v2[slot][wave] = t.v2;
@@ -355,8 +404,8 @@ CTP_DEV void reduce_pass(Top2& t, double& rv, int& ri, int slot) {
     }
   }
   __syncthreads();
-  // lane w of every wave takes wave w's partial, a butterfly over the first
-  // NT / 64 lanes merges them, lane 0's result is broadcast
+  // lane w of every wave takes wave w's partial, the same butterfly over the
+  // first NT / 64 lanes merges them, lane 0's result is broadcast
   constexpr int NW = NT / 64;
   Top2 u = top2_empty();
   double bv = -1.0;
@@ -369,23 +418,15 @@ CTP_DEV void reduce_pass(Top2& t, double& rv, int& ri, int slot) {
       bi = pv_sh.ri[slot][lane];
     }
   }
-  for (int off = NW / 2; off > 0; off >>= 1) {
-    const double o1 = __shfl_xor(u.v1, off, 64), o2 = __shfl_xor(u.v2, off, 64);
-    top2_merge(u, o1, o2);
-    if (ARG) {
-      const double ov = __shfl_xor(bv, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (pv_better(ov, oi, bv, bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-  }
-  t.v1 = __shfl(u.v1, 0, 64);
-  t.v2 = __shfl(u.v2, 0, 64);
+  if constexpr (NW > 1) red_round_dpp<ARG, DPP_XOR1>(u, bv, bi);
+  if constexpr (NW > 2) red_round_dpp<ARG, DPP_XOR2>(u, bv, bi);
+  if constexpr (NW > 4) red_round_dpp<ARG, DPP_HALF_MIRROR>(u, bv, bi);
+  if constexpr (NW > 8) red_round_dpp<ARG, DPP_MIRROR>(u, bv, bi);
+  t.v1 = first_lane_dbl(u.v1);
+  t.v2 = first_lane_dbl(u.v2);
   if (ARG) {
-    rv = __shfl(bv, 0, 64);
-    ri = __shfl(bi, 0, 64);
+    rv = first_lane_dbl(bv);
+    ri = __builtin_amdgcn_readfirstlane(bi);
   }
 }
 
