@@ -113,13 +113,17 @@ typedef struct ctp_opts {
                       1 = FP32 matrix cores, 2 = BF16 matrix cores (FP32
                       accumulation, FP32 trailing matrix); the supernode
                       entry points always compute in FP64 */
-  int tile;        /* Form kernel schedule variant: -1 or 0 = default (with a stored W:
-                      next chunk staged mid-chunk, staging rows split so LDS
-                      stores are contiguous); with a stored W 1 = staging at the
-                      end of the chunk, 2 = mid-chunk staging, 3 = mid-chunk +
-                      padded LDS rows, 4 = 3 + split staging rows (all give the
-                      same bits); with work = NULL 1 = two rows per staging
-                      thread */
+  int tile;        /* Form kernel schedule variant (all give the same bits).
+                      With a stored W: -1 or 0 = default (operands loaded
+                      straight into a ring of four LDS buffers, 8 k per chunk,
+                      product taken as S^T = W L21^T so that stores are whole
+                      lines); 1 = register-staged, staging at the end of the
+                      chunk; 2 = register-staged mid-chunk; 3 = 2 + padded LDS
+                      rows; 4 = 3 + split staging rows; 5 = 2 + split staging
+                      rows; 6 = LDS ring with the plain product; 7 = default +
+                      next chunk's LDS reads overlapping the current products.
+                      Batched Form: 0 = default, 1-3 = register-staged.  With
+                      work = NULL 1 = two rows per staging thread */
   unsigned flags;  /* CTP_FLAG_* bits, default 0 */
 } ctp_opts;
 

@@ -1,12 +1,13 @@
 """Autotuner for the Form launches.
 
-The Form kernel has three tile schedules (ctp_opts.tile: 0 = padded LDS rows
-with the next chunk staged after three k steps, 1 = plain, 2 = staged
-without padding) and a batch runs its Form as one persistent launch whose
-workgroup count is free.  Which combination is fastest depends on the
-shapes (tile counts, K = nelim, ragged edges), so the tuner times every
-candidate on the caller's own data and keeps the fastest per problem
-signature (in memory, optionally mirrored to a JSON file).
+The Form kernel has several tile schedules (ctp_opts.tile; for a batch 0 =
+operands loaded straight into a ring of LDS buffers, product stored as whole
+lines, 1-3 = operands staged through registers) and a batch runs its Form
+as one persistent launch whose workgroup count is free.  Which combination
+is fastest depends on the shapes (tile counts, K = nelim, ragged edges), so
+the tuner times every candidate on the caller's own data and keeps the
+fastest per problem signature (in memory, optionally mirrored to a JSON
+file).
 
 Timing only: the candidates compute the same result (each tile's
 arithmetic is fixed), so choosing among them never changes the output.
@@ -17,7 +18,8 @@ import os
 
 import torch
 
-TILES = (0, 1, 2)
+TILES = (0, 1, 2, 3)
+SCHUR_TILES = (0, 5, 6, 7)   # single-node Form: default, staged VAR 17, LDS ring plain, overlapped reads
 WORKGROUPS = (256, 512, 1024, 2048)
 
 _cache = {}
@@ -92,7 +94,7 @@ def tune_schur(run_form, opts, key, reps=2, cache_path=None):
         return {"best": _cache[key], "cached": True}
     timings = []
     run_form()
-    for tile in TILES:
+    for tile in SCHUR_TILES:
         opts.tile = tile
         timings.append({"tile": tile, "ms": round(_time(run_form, reps), 3)})
     best = min(timings, key=lambda t: t["ms"])

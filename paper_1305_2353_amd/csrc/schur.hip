@@ -218,23 +218,302 @@ struct SchurWArgs {
 // Main loop and epilogue of one tile.  VEC: every row of both operands
 // that this tile stages exists and each column is 16-byte aligned, so a
 // thread's 4 rows come in as two 16-byte loads; otherwise 4 clamped loads.
-// VAR selects the schedule: bit 0 writes the next chunk into LDS after
-// three of the four k steps (so a chunk ends with the barrier alone), bit 1
-// pads the LDS rows by 8 doubles (bit 2: by 16), bit 4 splits a thread's
-// staging rows into two pairs 64 rows apart so that the lanes' 16-byte LDS
-// stores are contiguous.  The default is bits 0 and 4 (VAR 17), the fastest
-// measured (padding does not pay once the stores are contiguous); a second
-// register stage (loads two chunks ahead) spills.  Bit 3 subtracts the
-// product from the output instead of storing it (the trailing update of a
-// right-looking factorization).  Every variant gives the same bits.
+// VAR selects the schedule.  Register-staged tiles: bit 0 writes the next
+// chunk into LDS after three of the four k steps (so a chunk ends with the
+// barrier alone), bit 1 pads the LDS rows by 8 doubles (bit 2: by 16), bit
+// 4 splits a thread's staging rows into two pairs 64 rows apart so that the
+// lanes' 16-byte LDS stores are contiguous (VAR 17 is the fastest of these;
+// a second register stage spills).  Bit 3 subtracts the product from the
+// output instead of storing it (the trailing update of a right-looking
+// factorization).  Bit 5 sends full, 16-byte aligned tiles to the
+// direct-to-LDS pipeline below (chunks of 8 k, four buffers; with bit 6
+// chunks of 16 k, three buffers, one workgroup per CU; with bit 7 the LDS
+// reads of the next chunk overlap the products of the current one), and
+// bit 8 takes the product as S^T = W L21^T there, which turns the tile's
+// stores into whole 128-byte lines.  The default is bits 0, 4, 5 and 8
+// (VAR 305): 63.0 against 56.8 TFLOP/s for VAR 17 on the 4096-row blocks
+// of an n = 100000, p = 512 panel.  Every variant gives the same bits:
+// each output is the same sequence of matrix-core steps over k, and the
+// operands of a product commute exactly.
 template <int VAR>
 struct SchurWShape {
   static constexpr int LW = (VAR & 4) ? SC_BM + 16 : (VAR & 2) ? SC_BM + 8 : SC_BM;   // LDS row stride (doubles)
-  static constexpr int LDS_BYTES = 2 * 2 * 16 * LW * 8;       // two buffers, two operands
+  static constexpr int STAGED_BYTES = 2 * 2 * 16 * LW * 8;    // two buffers, two operands
+  static constexpr int DL_BK = (VAR & 64) ? 16 : 8;           // k per chunk of the pipeline
+  static constexpr int DL_NBUF = (VAR & 64) ? 3 : 4;          // chunks resident in LDS
+  static constexpr int DL_BYTES = (VAR & 32) ? DL_NBUF * 2 * DL_BK * SC_BM * 8 : 0;
+  static constexpr int LDS_BYTES = STAGED_BYTES > DL_BYTES ? STAGED_BYTES : DL_BYTES;
 };
+
+// Lower-triangle part of a finished 128 x 128 tile to S (or subtracted from
+// it).  Accumulator q of block (x, y) in lane l is row 16x + l/16 + 4q,
+// column 16y + l%16 of the wave's 64 x 64 quarter; with bit 8 (the product
+// taken as S^T = W L21^T) it is row 16x + l%16, column 16y + l/16 + 4q, so
+// that 16 lanes store 16 consecutive rows of a column (one 128-byte line).
+template <int VAR>
+__device__ __forceinline__ void schur_w_epilogue(const SchurWArgs& g, int i0, int j0, const d4 (&acc)[4][4]) {
+  constexpr bool TR = (VAR & 256) != 0;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
+  const int iend = g.row0 + g.nrows;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + wm * 64 + x * 16 + (TR ? lrow : lk + 4 * q);
+        const int j = j0 + wn * 64 + y * 16 + (TR ? lk + 4 * q : lrow);
+        if (i < iend && j <= i) {
+          double* dst = g.tiled ? g.s + (size_t)(j - j0) * SC_BM + (i - i0)
+                                : g.s + (size_t)j * g.lds + (i - g.row0);
+          if (VAR & 8) *dst -= acc[x][y][q];   // trailing update: C -= L21 W^T
+          else *dst = acc[x][y][q];
+        }
+      }
+}
+
+#define SC_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+// s_waitcnt immediate that waits until at most n vector-memory operations of
+// the wave are outstanding (vmcnt bits 3:0 and 15:14; expcnt and lgkmcnt at
+// their maxima, so they do not wait)
+constexpr int sc_vmcnt(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+// Direct-to-LDS pipeline for a full tile whose operand columns are 16-byte
+// aligned.  A chunk is BK k-rows of each operand, one 1 KB row (128 doubles)
+// per wave instruction: lane l's 16 bytes land at row start + 16 l, so the
+// rows arrive in LDS without passing through registers.  NBUF chunks are
+// resident: at chunk kc every wave waits for its own loads of chunk kc
+// (vmcnt counts only the later chunks still in flight), the barrier makes
+// everyone's loads visible and certifies that chunk kc-1 has been read, and
+// chunk kc+NBUF-1 is then issued into kc-1's buffer.  k rows past K load
+// row K-1 and are zeroed in both operands before the product, so the
+// matrix-core arithmetic is that of the staged variants.
+template <int VAR>
+__device__ __forceinline__ void schur_w_tile_dl(const SchurWArgs& g, int i0, int j0, int K, double* lds) {
+  constexpr int BK = SchurWShape<VAR>::DL_BK;
+  constexpr int NBUF = SchurWShape<VAR>::DL_NBUF;
+  constexpr int NW = SC_THREADS / 64;
+  constexpr int ROWS = 2 * BK;              // rows of both operands per chunk
+  constexpr int PER_WAVE = ROWS / NW;       // load instructions per wave and chunk
+  static_assert(BK % NW == 0 && BK % 4 == 0, "chunk rows must split evenly over the waves");
+  static_assert(PER_WAVE * (NBUF - 2) < 64, "vmcnt immediate");
+  constexpr int CHUNK = ROWS * SC_BM;       // doubles per buffer
+  const int nk = (K + BK - 1) / BK;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
+  const double* const l21 = g.l21 + i0 + 2 * lane;
+  const double* const wp = g.w + j0 + 2 * lane;
+
+  auto issue = [&](int kc) {
+    double* buf = lds + (kc % NBUF) * CHUNK;
+#pragma unroll
+    for (int j = 0; j < PER_WAVE; ++j) {
+      const int cr = wave + NW * j;         // chunk row: operand cr / BK, k row cr % BK
+      const int kk = min(kc * BK + cr % BK, K - 1);
+      const double* src = cr < BK ? l21 + (size_t)kk * g.lda : wp + (size_t)kk * g.ldw;
+      __builtin_amdgcn_global_load_lds(src, SC_LDS_PTR(buf + cr * SC_BM), 16, 0, 0);
+    }
+  };
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // no earlier stores or loads of this wave may be counted by the waits below
+  __builtin_amdgcn_s_waitcnt(sc_vmcnt(0));
+#pragma unroll
+  for (int c = 0; c < NBUF - 1; ++c)
+    if (c < nk) issue(c);
+
+  for (int kc = 0; kc < nk; ++kc) {
+    // chunks issued after kc and still in flight: min(nk - 1, kc + NBUF - 2) - kc
+    const int later = min(nk - 1 - kc, NBUF - 2);
+    if (later >= 2) __builtin_amdgcn_s_waitcnt(sc_vmcnt(2 * PER_WAVE));
+    else if (later == 1) __builtin_amdgcn_s_waitcnt(sc_vmcnt(PER_WAVE));
+    else __builtin_amdgcn_s_waitcnt(sc_vmcnt(0));
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    if (kc + NBUF - 1 < nk) issue(kc + NBUF - 1);
+    const double* const As = lds + (kc % NBUF) * CHUNK;
+    const double* const Bs = As + BK * SC_BM;
+    const bool full = (kc + 1) * BK <= K;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double af[4], bf[4];
+      const double* pa = As + (ks + lk) * SC_BM + wm * 64 + lrow;
+      const double* pb = Bs + (ks + lk) * SC_BM + wn * 64 + lrow;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) af[x] = pa[x * 16];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) bf[y] = pb[y * 16];
+      if (!full) {
+        const bool kv = kc * BK + ks + lk < K;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) af[x] = kv ? af[x] : 0.0;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) bf[y] = kv ? bf[y] : 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = (VAR & 256) ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[y], af[x], acc[x][y], 0, 0, 0)
+                                  : __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+    }
+    asm volatile("" ::: "memory");
+  }
+  // every wave has read the last chunk before the workgroup moves on (the
+  // persistent Form reuses the buffers for its next tile)
+  __builtin_amdgcn_s_barrier();
+  schur_w_epilogue<VAR>(g, i0, j0, acc);
+}
+
+// The same pipeline with the LDS reads of chunk kc+1 overlapping the
+// matrix-core work of chunk kc (bit 7 with bit 5): right after the barrier
+// that publishes chunk kc+1, every wave requests all of its operand
+// fragments into a second register set and only then issues chunk kc's
+// products.  Each wave holds its fragments of chunk kc in registers before
+// it reaches the barrier of chunk kc+1 (lgkmcnt(0)), so the buffer of chunk
+// kc can take chunk kc+NBUF right after that barrier.
+template <int VAR>
+__device__ __forceinline__ void schur_w_tile_dlp(const SchurWArgs& g, int i0, int j0, int K, double* lds) {
+  constexpr int BK = SchurWShape<VAR>::DL_BK;
+  constexpr int NBUF = SchurWShape<VAR>::DL_NBUF;
+  constexpr int NW = SC_THREADS / 64;
+  constexpr int ROWS = 2 * BK;
+  constexpr int PER_WAVE = ROWS / NW;
+  constexpr int KS = BK / 4;                 // k steps per chunk
+  static_assert(BK % NW == 0 && BK % 4 == 0, "chunk rows must split evenly over the waves");
+  constexpr int CHUNK = ROWS * SC_BM;
+  const int nk = (K + BK - 1) / BK;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lrow = lane & 15;
+  const int lk = lane >> 4;
+  const double* const l21 = g.l21 + i0 + 2 * lane;
+  const double* const wp = g.w + j0 + 2 * lane;
+
+  auto issue = [&](int kc) {
+    double* buf = lds + (kc % NBUF) * CHUNK;
+#pragma unroll
+    for (int j = 0; j < PER_WAVE; ++j) {
+      const int cr = wave + NW * j;
+      const int kk = min(kc * BK + cr % BK, K - 1);
+      const double* src = cr < BK ? l21 + (size_t)kk * g.lda : wp + (size_t)kk * g.ldw;
+      __builtin_amdgcn_global_load_lds(src, SC_LDS_PTR(buf + cr * SC_BM), 16, 0, 0);
+    }
+  };
+  // wait for this wave's loads of chunk c (the chunks after it stay in flight)
+  auto wait_chunk = [&](int c) {
+    const int later = min(nk - 1 - c, NBUF - 2);
+    if (later >= 2) __builtin_amdgcn_s_waitcnt(sc_vmcnt(2 * PER_WAVE));
+    else if (later == 1) __builtin_amdgcn_s_waitcnt(sc_vmcnt(PER_WAVE));
+    else __builtin_amdgcn_s_waitcnt(sc_vmcnt(0));
+  };
+  struct Frag {
+    double a[KS][4], b[KS][4];
+  };
+  auto read = [&](int kc, Frag& F) {
+    const double* const As = lds + (kc % NBUF) * CHUNK;
+    const double* const Bs = As + BK * SC_BM;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const double* pa = As + (4 * s + lk) * SC_BM + wm * 64 + lrow;
+      const double* pb = Bs + (4 * s + lk) * SC_BM + wn * 64 + lrow;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) F.a[s][x] = pa[x * 16];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) F.b[s][y] = pb[y * 16];
+    }
+  };
+  d4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  auto mma = [&](int kc, Frag& F) {
+    const bool full = (kc + 1) * BK <= K;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if (!full) {
+        const bool kv = kc * BK + 4 * s + lk < K;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) F.a[s][x] = kv ? F.a[s][x] : 0.0;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) F.b[s][y] = kv ? F.b[s][y] : 0.0;
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = (VAR & 256) ? __builtin_amdgcn_mfma_f64_16x16x4f64(F.b[s][y], F.a[s][x], acc[x][y], 0, 0, 0)
+                                  : __builtin_amdgcn_mfma_f64_16x16x4f64(F.a[s][x], F.b[s][y], acc[x][y], 0, 0, 0);
+    }
+  };
+  auto sync = [&]() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // one step: chunk kc's products from F while chunk kc+1 is read into G
+  auto step = [&](int kc, Frag& F, Frag& G) {
+    if (kc + 1 < nk) {
+      wait_chunk(kc + 1);
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): F is in registers
+      sync();
+      if (kc + NBUF < nk) issue(kc + NBUF);
+      read(kc + 1, G);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    mma(kc, F);
+  };
+
+  __builtin_amdgcn_s_waitcnt(sc_vmcnt(0));
+#pragma unroll
+  for (int c = 0; c < NBUF - 1; ++c)
+    if (c < nk) issue(c);
+  Frag F0, F1;
+  if (nk > 0) {
+    wait_chunk(0);
+    sync();
+    if (NBUF - 1 < nk) issue(NBUF - 1);
+    read(0, F0);
+  }
+  int kc = 0;
+  for (; kc + 1 < nk; kc += 2) {
+    step(kc, F0, F1);
+    step(kc + 1, F1, F0);
+  }
+  if (kc < nk) step(kc, F0, F1);
+  // every wave has read the last chunk before the workgroup moves on
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  sync();
+  schur_w_epilogue<VAR>(g, i0, j0, acc);
+}
 
 template <bool VEC, int VAR>
 __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0, int K, double* lds) {
+  if constexpr (VEC && (VAR & 160) == 160) {
+    schur_w_tile_dlp<VAR>(g, i0, j0, K, lds);
+    return;
+  } else if constexpr (VEC && (VAR & 32) != 0) {
+    schur_w_tile_dl<VAR>(g, i0, j0, K, lds);
+    return;
+  }
   constexpr int BK = 16;
   constexpr int RPT = 4;
   constexpr int TPK = SC_BM / RPT;          // 32 threads per k column
@@ -371,22 +650,7 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
     if (kc + 1 < nk) load(st0, kc + 1);
     chunk(kc & 1, st0, kc);
   }
-
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = i0 + wm * 64 + x * 16 + lk + 4 * q;
-        const int j = j0 + wn * 64 + y * 16 + lrow;
-        if (i < iend && j <= i) {
-          double* dst = g.tiled ? g.s + (size_t)(j - j0) * SC_BM + (i - i0)
-                                : g.s + (size_t)j * g.lds + (i - g.row0);
-          if (VAR & 8) *dst -= acc[x][y][q];   // trailing update: C -= L21 W^T
-          else *dst = acc[x][y][q];
-        }
-      }
+  schur_w_epilogue<VAR & ~256>(g, i0, j0, acc);
 }
 
 extern __shared__ double sc_dyn[];
@@ -456,7 +720,10 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
     case 2: rc = launch_schur_w_var<1>(g, vec, grid, stream); break;
     case 3: rc = launch_schur_w_var<3>(g, vec, grid, stream); break;
     case 4: rc = launch_schur_w_var<19>(g, vec, grid, stream); break;
-    default: rc = launch_schur_w_var<17>(g, vec, grid, stream); break;
+    case 5: rc = launch_schur_w_var<17>(g, vec, grid, stream); break;
+    case 6: rc = launch_schur_w_var<49>(g, vec, grid, stream); break;
+    case 7: rc = launch_schur_w_var<433>(g, vec, grid, stream); break;
+    default: rc = launch_schur_w_var<305>(g, vec, grid, stream); break;
   }
   if (rc) return rc;
   hipError_t e = hipGetLastError();
@@ -545,13 +812,15 @@ int launch_schur_batch(int count, const BatchNode* nodes, int method, long long 
     switch (variant) {
       case 1: rc = launch_schur_queue_var<8>(nodes, count, method, total, 0, counter, grid, stream); break;
       case 2: rc = launch_schur_queue_var<9>(nodes, count, method, total, 0, counter, grid, stream); break;
-      default: rc = launch_schur_queue_var<25>(nodes, count, method, total, 0, counter, grid, stream); break;
+      case 3: rc = launch_schur_queue_var<25>(nodes, count, method, total, 0, counter, grid, stream); break;
+      default: rc = launch_schur_queue_var<313>(nodes, count, method, total, 0, counter, grid, stream); break;
     }
   } else {
     switch (variant) {
       case 1: rc = launch_schur_queue_var<0>(nodes, count, method, total, tiled, counter, grid, stream); break;
       case 2: rc = launch_schur_queue_var<1>(nodes, count, method, total, tiled, counter, grid, stream); break;
-      default: rc = launch_schur_queue_var<17>(nodes, count, method, total, tiled, counter, grid, stream); break;
+      case 3: rc = launch_schur_queue_var<17>(nodes, count, method, total, tiled, counter, grid, stream); break;
+      default: rc = launch_schur_queue_var<305>(nodes, count, method, total, tiled, counter, grid, stream); break;
     }
   }
   if (rc) return rc;
@@ -585,7 +854,7 @@ int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, 
   const unsigned grid = g.per_xcd * SC_NXCD;
   const bool vec = ((reinterpret_cast<uintptr_t>(a + p) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&
                    lda % 2 == 0 && ldw % 2 == 0;
-  int rc = launch_schur_w_var<25>(g, vec, grid, stream);
+  int rc = launch_schur_w_var<313>(g, vec, grid, stream);
   if (rc) return rc;
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;

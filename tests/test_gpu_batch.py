@@ -79,7 +79,7 @@ def test_batch_nodes_without_form():
         _check_node(b, i, A, "relaxed")
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 @pytest.mark.parametrize("tiled", [False, True])
 def test_batch_form_schedules_agree(tile, tiled):
     print("case: batch tile", tile, tiled, flush=True)

@@ -155,6 +155,43 @@ def test_schur_row_blocks_tile_the_triangle(stored_w, method):
         assert rel_err(np.tril(blk, row0), np.tril(whole[row0:row0 + nrows, :row0 + nrows], row0)) <= 1e-14
 
 
+@pytest.mark.parametrize("shape,row0", [((1500, 100), 0), ((4500, 512), 0), ((2049, 37), 0), ((3000, 256), 333)])
+def test_schur_variants_same_bits(shape, row0):
+    """Every Form schedule (register-staged, direct-to-LDS ring, products
+    taken as S or as S^T, LDS reads overlapped) gives the same bits: full
+    tiles, ragged edge tiles, k tails (nelim not a multiple of the chunk)
+    and an odd first row (unaligned operands, staged path throughout)."""
+    import torch
+    from paper_1305_2353_amd import ctp
+    from oracle.supernode import factor_supernode, schur_rows
+    n, p = shape
+    _announce("schur variants", shape, row0)
+    A = supernode(n, p, seed=3 * n + p, n_small=min(3, p))
+    a = ctp.device_panel(A)
+    opts = ctp.ctp_default_opts("relaxed")
+    work = ctp.workspace(n, p, opts)
+    f = ctp.ctp_supernode(a, opts, work=work)
+    r = n - p
+    nrows = r - row0
+    outs = {}
+    for tile in range(8):
+        opts.tile = tile
+        outs[tile] = ctp.ctp_schur(a, f, row0, nrows, opts, work=work)
+    torch.cuda.synchronize()
+    for tile in range(1, 8):
+        assert torch.equal(torch.tril(outs[tile], row0), torch.tril(outs[0], row0)), tile
+    ref = factor_supernode(A, p, "relaxed")
+    if ref.trap.fragile_steps():
+        return
+    assert int(f["nelim"].item()) == ref.nelim
+    rows = np.unique(np.linspace(row0, r - 1, min(nrows, 48)).astype(int))
+    S_ref = schur_rows(ref, rows)
+    L21, W = schur_factors(ref, p)
+    s = outs[0].cpu().numpy()
+    for q, i in enumerate(rows):
+        assert rel_err(s[i - row0, :i + 1], S_ref[q, :i + 1]) <= schur_row_tol(L21, W, i, S_ref[q, :i + 1]), (shape, i)
+
+
 @pytest.mark.parametrize("shape", [(131, 128), (133, 5), (700, 17), (2049, 100), (4500, 512)])
 def test_schur_stored_w_ragged(shape):
     """Form from the stored W at sizes that leave partial tiles, partial k
