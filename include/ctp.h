@@ -120,8 +120,7 @@ typedef struct ctp_opts {
                       lines); 1 = register-staged, staging at the end of the
                       chunk; 2 = register-staged mid-chunk; 3 = 2 + padded LDS
                       rows; 4 = 3 + split staging rows; 5 = 2 + split staging
-                      rows; 6 = LDS ring with the plain product; 7 = default +
-                      next chunk's LDS reads overlapping the current products.
+                      rows; 6 = LDS ring with the plain product.
                       Batched Form: 0 = default, 1-3 = register-staged.  With
                       work = NULL 1 = two rows per staging thread */
   unsigned flags;  /* CTP_FLAG_* bits, default 0 */

@@ -19,7 +19,7 @@ import os
 import torch
 
 TILES = (0, 1, 2, 3)
-SCHUR_TILES = (0, 5, 6, 7)   # single-node Form: default, staged VAR 17, LDS ring plain, overlapped reads
+SCHUR_TILES = (0, 5, 6)   # single-node Form: default, register-staged, LDS ring with the plain product
 WORKGROUPS = (256, 512, 1024, 2048)
 
 _cache = {}

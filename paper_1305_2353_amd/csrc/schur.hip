@@ -227,12 +227,15 @@ struct SchurWArgs {
 // output instead of storing it (the trailing update of a right-looking
 // factorization).  Bit 5 sends full, 16-byte aligned tiles to the
 // direct-to-LDS pipeline below (chunks of 8 k, four buffers; with bit 6
-// chunks of 16 k, three buffers, one workgroup per CU; with bit 7 the LDS
-// reads of the next chunk overlap the products of the current one), and
-// bit 8 takes the product as S^T = W L21^T there, which turns the tile's
-// stores into whole 128-byte lines.  The default is bits 0, 4, 5 and 8
-// (VAR 305): 63.0 against 56.8 TFLOP/s for VAR 17 on the 4096-row blocks
-// of an n = 100000, p = 512 panel.  Every variant gives the same bits:
+// chunks of 16 k, three buffers, one workgroup per CU), and bit 8 takes the
+// product as S^T = W L21^T there, which turns the tile's stores into whole
+// 128-byte lines.  The default is bits 0, 4, 5 and 8 (VAR 305): 63.0
+// against 56.8 TFLOP/s for VAR 17 on the 4096-row blocks of an n = 100000,
+// p = 512 panel.  Measured without gain and not kept: LDS reads of the next
+// chunk issued ahead of the current products (two waves per SIMD already
+// hide them), two buffers of 16 k, non-temporal or paired 16-byte stores
+// (the tiles of a launch finish together and their stores meet the HBM
+// write bandwidth as one burst).  Every variant gives the same bits:
 // each output is the same sequence of matrix-core steps over k, and the
 // operands of a product commute exactly.
 template <int VAR>
@@ -380,137 +383,9 @@ __device__ __forceinline__ void schur_w_tile_dl(const SchurWArgs& g, int i0, int
   schur_w_epilogue<VAR>(g, i0, j0, acc);
 }
 
-// The same pipeline with the LDS reads of chunk kc+1 overlapping the
-// matrix-core work of chunk kc (bit 7 with bit 5): right after the barrier
-// that publishes chunk kc+1, every wave requests all of its operand
-// fragments into a second register set and only then issues chunk kc's
-// products.  Each wave holds its fragments of chunk kc in registers before
-// it reaches the barrier of chunk kc+1 (lgkmcnt(0)), so the buffer of chunk
-// kc can take chunk kc+NBUF right after that barrier.
-template <int VAR>
-__device__ __forceinline__ void schur_w_tile_dlp(const SchurWArgs& g, int i0, int j0, int K, double* lds) {
-  constexpr int BK = SchurWShape<VAR>::DL_BK;
-  constexpr int NBUF = SchurWShape<VAR>::DL_NBUF;
-  constexpr int NW = SC_THREADS / 64;
-  constexpr int ROWS = 2 * BK;
-  constexpr int PER_WAVE = ROWS / NW;
-  constexpr int KS = BK / 4;                 // k steps per chunk
-  static_assert(BK % NW == 0 && BK % 4 == 0, "chunk rows must split evenly over the waves");
-  constexpr int CHUNK = ROWS * SC_BM;
-  const int nk = (K + BK - 1) / BK;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int lrow = lane & 15;
-  const int lk = lane >> 4;
-  const double* const l21 = g.l21 + i0 + 2 * lane;
-  const double* const wp = g.w + j0 + 2 * lane;
-
-  auto issue = [&](int kc) {
-    double* buf = lds + (kc % NBUF) * CHUNK;
-#pragma unroll
-    for (int j = 0; j < PER_WAVE; ++j) {
-      const int cr = wave + NW * j;
-      const int kk = min(kc * BK + cr % BK, K - 1);
-      const double* src = cr < BK ? l21 + (size_t)kk * g.lda : wp + (size_t)kk * g.ldw;
-      __builtin_amdgcn_global_load_lds(src, SC_LDS_PTR(buf + cr * SC_BM), 16, 0, 0);
-    }
-  };
-  // wait for this wave's loads of chunk c (the chunks after it stay in flight)
-  auto wait_chunk = [&](int c) {
-    const int later = min(nk - 1 - c, NBUF - 2);
-    if (later >= 2) __builtin_amdgcn_s_waitcnt(sc_vmcnt(2 * PER_WAVE));
-    else if (later == 1) __builtin_amdgcn_s_waitcnt(sc_vmcnt(PER_WAVE));
-    else __builtin_amdgcn_s_waitcnt(sc_vmcnt(0));
-  };
-  struct Frag {
-    double a[KS][4], b[KS][4];
-  };
-  auto read = [&](int kc, Frag& F) {
-    const double* const As = lds + (kc % NBUF) * CHUNK;
-    const double* const Bs = As + BK * SC_BM;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const double* pa = As + (4 * s + lk) * SC_BM + wm * 64 + lrow;
-      const double* pb = Bs + (4 * s + lk) * SC_BM + wn * 64 + lrow;
-#pragma unroll
-      for (int x = 0; x < 4; ++x) F.a[s][x] = pa[x * 16];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) F.b[s][y] = pb[y * 16];
-    }
-  };
-  d4 acc[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-  auto mma = [&](int kc, Frag& F) {
-    const bool full = (kc + 1) * BK <= K;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      if (!full) {
-        const bool kv = kc * BK + 4 * s + lk < K;
-#pragma unroll
-        for (int x = 0; x < 4; ++x) F.a[s][x] = kv ? F.a[s][x] : 0.0;
-#pragma unroll
-        for (int y = 0; y < 4; ++y) F.b[s][y] = kv ? F.b[s][y] : 0.0;
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-          acc[x][y] = (VAR & 256) ? __builtin_amdgcn_mfma_f64_16x16x4f64(F.b[s][y], F.a[s][x], acc[x][y], 0, 0, 0)
-                                  : __builtin_amdgcn_mfma_f64_16x16x4f64(F.a[s][x], F.b[s][y], acc[x][y], 0, 0, 0);
-    }
-  };
-  auto sync = [&]() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-  };
-  // one step: chunk kc's products from F while chunk kc+1 is read into G
-  auto step = [&](int kc, Frag& F, Frag& G) {
-    if (kc + 1 < nk) {
-      wait_chunk(kc + 1);
-      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): F is in registers
-      sync();
-      if (kc + NBUF < nk) issue(kc + NBUF);
-      read(kc + 1, G);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    mma(kc, F);
-  };
-
-  __builtin_amdgcn_s_waitcnt(sc_vmcnt(0));
-#pragma unroll
-  for (int c = 0; c < NBUF - 1; ++c)
-    if (c < nk) issue(c);
-  Frag F0, F1;
-  if (nk > 0) {
-    wait_chunk(0);
-    sync();
-    if (NBUF - 1 < nk) issue(NBUF - 1);
-    read(0, F0);
-  }
-  int kc = 0;
-  for (; kc + 1 < nk; kc += 2) {
-    step(kc, F0, F1);
-    step(kc + 1, F1, F0);
-  }
-  if (kc < nk) step(kc, F0, F1);
-  // every wave has read the last chunk before the workgroup moves on
-  __builtin_amdgcn_s_waitcnt(0xC07F);
-  sync();
-  schur_w_epilogue<VAR>(g, i0, j0, acc);
-}
-
 template <bool VEC, int VAR>
 __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0, int K, double* lds) {
-  if constexpr (VEC && (VAR & 160) == 160) {
-    schur_w_tile_dlp<VAR>(g, i0, j0, K, lds);
-    return;
-  } else if constexpr (VEC && (VAR & 32) != 0) {
+  if constexpr (VEC && (VAR & 32) != 0) {
     schur_w_tile_dl<VAR>(g, i0, j0, K, lds);
     return;
   }
@@ -722,7 +597,6 @@ int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int 
     case 4: rc = launch_schur_w_var<19>(g, vec, grid, stream); break;
     case 5: rc = launch_schur_w_var<17>(g, vec, grid, stream); break;
     case 6: rc = launch_schur_w_var<49>(g, vec, grid, stream); break;
-    case 7: rc = launch_schur_w_var<433>(g, vec, grid, stream); break;
     default: rc = launch_schur_w_var<305>(g, vec, grid, stream); break;
   }
   if (rc) return rc;

@@ -158,7 +158,7 @@ def test_schur_row_blocks_tile_the_triangle(stored_w, method):
 @pytest.mark.parametrize("shape,row0", [((1500, 100), 0), ((4500, 512), 0), ((2049, 37), 0), ((3000, 256), 333)])
 def test_schur_variants_same_bits(shape, row0):
     """Every Form schedule (register-staged, direct-to-LDS ring, products
-    taken as S or as S^T, LDS reads overlapped) gives the same bits: full
+    taken as S or as S^T) gives the same bits: full
     tiles, ragged edge tiles, k tails (nelim not a multiple of the chunk)
     and an odd first row (unaligned operands, staged path throughout)."""
     import torch
@@ -174,11 +174,11 @@ def test_schur_variants_same_bits(shape, row0):
     r = n - p
     nrows = r - row0
     outs = {}
-    for tile in range(8):
+    for tile in range(7):
         opts.tile = tile
         outs[tile] = ctp.ctp_schur(a, f, row0, nrows, opts, work=work)
     torch.cuda.synchronize()
-    for tile in range(1, 8):
+    for tile in range(1, 7):
         assert torch.equal(torch.tril(outs[tile], row0), torch.tril(outs[0], row0)), tile
     ref = factor_supernode(A, p, "relaxed")
     if ref.trap.fragile_steps():
