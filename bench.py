@@ -41,8 +41,8 @@ BLOCK_ROWS = 4096
 # of the n=100000, p=512 step, valid only for the kernel source they were
 # measured on.
 FORM_COUNTERS = {
-    "source_sha256": "f28fcdbc0b05e4bf4ede0be58c3a6f39f737a2db98617af4af146b046b0ccc36",
-    "hbm_bytes_per_launch": 3993212116,
+    "source_sha256": "ba551cc55bdbc8b9d4fa6c3984bd307281e7bb555c06459716e5941c777a88db",
+    "hbm_bytes_per_launch": 3938416464,
     "n": 100000, "p": 512,
 }
 
