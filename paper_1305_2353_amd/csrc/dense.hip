@@ -408,7 +408,22 @@ __global__ __launch_bounds__(RES_ROWS) void dense_residual_kernel(const double* 
   double acc[SW_MAXRHS];
   for (int c = 0; c < SW_MAXRHS; ++c) acc[c] = 0.0;
   double as = 0.0;
-  for (int j = j0; j < j1; ++j) {
+  // eight column loads in flight before their products (the products and
+  // the row sum still run in column order)
+  int j = j0;
+  for (; j + 8 <= j1; j += 8) {
+    double av[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) av[u] = A[(size_t)(j + u) * lda + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      as += fabs(av[u]);
+#pragma unroll
+      for (int c = 0; c < SW_MAXRHS; ++c)
+        if (c < nrhs) acc[c] = fma(av[u], xs[c][j + u - j0], acc[c]);
+    }
+  }
+  for (; j < j1; ++j) {
     const double aij = A[(size_t)j * lda + i];
     as += fabs(aij);
 #pragma unroll

@@ -16,6 +16,10 @@
 //    BF16: v_mfma_f32_16x16x32_bf16, lane l holds A(l%16, k0 + 8(l/16) + v)
 //          and B(k0 + 8(l/16) + v, l%16), v = 0..7;
 //    both: accumulator element q of lane l is row 4(l/16) + q, column l%16.
+//    The product is taken as C^T's block (W fragments as the A operand), so
+//    16 lanes of an accumulator hold 16 consecutive rows i of one column j
+//    of C and the read-modify-write of C touches 64-byte runs (with L21 as
+//    the A operand the rows of a lane group were 4 apart).
 
 #include "common.h"
 
@@ -156,7 +160,7 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int y = 0; y < 4; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[x], bf[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(bf[y], af[x], acc[x][y], 0, 0, 0);
       }
     } else {
 #pragma unroll
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int y = 0; y < 4; ++y)
-            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[x], bf[y], acc[x][y], 0, 0, 0);
+            acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[y], af[x], acc[x][y], 0, 0, 0);
       }
     }
     if (kc + 1 < nk) store(buf ^ 1);
@@ -185,8 +189,8 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
     for (int y = 0; y < 4; ++y)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = i0 + wm * 64 + x * 16 + 4 * lk + q;
-        const int j = j0 + wn * 64 + y * 16 + lrow;
+        const int i = i0 + wm * 64 + x * 16 + lrow;
+        const int j = j0 + wn * 64 + y * 16 + 4 * lk + q;
         if (i < g.r && j <= i) g.c[(size_t)j * g.ldc + i] -= acc[x][y][q];
       }
 }

@@ -455,11 +455,8 @@ CTP_DEV SwapPlan swap_plan(int a0, int b0, int a1, int b1) {
 
 // Moves the entries at the plan's positions of one line (a row or a column,
 // reached through ld / st): every value is read before any is written.
-template <typename V, typename Ld, typename St>
-CTP_DEV void permute_line(const SwapPlan& s, Ld&& ld, St&& st) {
-  V v[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) v[q] = ld(s.x[q]);
+template <typename V, typename St>
+CTP_DEV void permute_store(const SwapPlan& s, const V (&v)[4], St&& st) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (s.src[q] == s.x[q]) continue;
@@ -469,6 +466,14 @@ CTP_DEV void permute_line(const SwapPlan& s, Ld&& ld, St&& st) {
       if (s.src[q] == s.x[e]) val = v[e];
     st(s.x[q], val);
   }
+}
+
+template <typename V, typename Ld, typename St>
+CTP_DEV void permute_line(const SwapPlan& s, Ld&& ld, St&& st) {
+  V v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = ld(s.x[q]);
+  permute_store<V>(s, v, st);
 }
 
 // Row half of the interchanges: the rows of the square (stored values and
@@ -694,6 +699,15 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
       i21 = -(f * d21);
       i22 = f * d1;
     }
+    // this thread's first cached R row: its interchange values are read
+    // here, so that they travel with the square's (one memory round trip
+    // for both halves of the column phase)
+    double rpre[4];
+    const bool rpre_ok = moves && (int)threadIdx.x < rc && (int)threadIdx.x < g.r;
+    if (rpre_ok) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rpre[q] = CM(g.R, threadIdx.x, sp.x[q], g.ldr);
+    }
     // the square: column half of the interchanges, then the pivot columns
     // (pivot-column values from the column buffers: old column m, and old
     // column t for a 2x2, at the row's old position)
@@ -740,9 +754,11 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
     const double j11 = fabs(i11), j21 = fabs(i21), j22 = fabs(i22);
     for_r_rows<NT>(rc, g.r, [&](int i, auto cached) {
       constexpr bool C = decltype(cached)::value;
-      if (moves)
-        permute_line<double>(sp, [&](int x) { return CM(g.R, i, x, g.ldr); },
-                             [&](int x, double v) { CM(g.R, i, x, g.ldr) = v; });
+      if (moves) {
+        auto st = [&](int x, double v) { CM(g.R, i, x, g.ldr) = v; };
+        if (C && rpre_ok && i == (int)threadIdx.x) permute_store<double>(sp, rpre, st);
+        else permute_line<double>(sp, [&](int x) { return CM(g.R, i, x, g.ldr); }, st);
+      }
       if (action == ACT_ZERO) {
         CM(g.R, i, k, g.ldr) = 0.0;
       } else if (!two) {
