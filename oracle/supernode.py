@@ -39,7 +39,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .threshold import (PIV_1X1, PIV_2X2_FIRST, PIV_2X2_SECOND, PIV_ZERO,
-                        R_ABS, R_NORMAL, factor_trapezoid)
+                        R_ABS, R_NORMAL, ST_NONFINITE, factor_trapezoid)
 
 METHODS = ("tpp", "strict", "relaxed", "restricted")
 
@@ -114,6 +114,7 @@ class SupernodeFactors:
     crow: np.ndarray      # relaxed: A21 row behind each C row (else None)
     log: list             # decision log of the pivot search
     trap: object          # the TrapezoidFactors of the pivot search
+    status: int = 0       # OR of the threshold.ST_* bits (see factor_supernode)
 
 
 def d_blocks(piv, d, nelim):
@@ -164,7 +165,7 @@ def solve_a21(A21P, L, piv, d, nelim):
             for j in range(k):
                 W[:, k] = W[:, k] - W[:, j] * L[k, j]
     elif nelim:
-        W = sla.solve_triangular(L[:nelim, :nelim], AE.T, lower=True,
+        W = sla.solve_triangular(L[:nelim, :nelim], AE.T, lower=True, check_finite=False,
                                  unit_diagonal=True).T
     else:
         W = np.zeros((r, 0), dtype=A21P.dtype)
@@ -198,6 +199,11 @@ def factor_supernode(A, p, method="relaxed", u=0.01, small=1e-20, forced=None, r
     A: n x p array; the lower triangle of its first p rows is A11.
     root: eliminate every column (last panel of a factorization; see
     factor_trapezoid).
+    status: the pivot search's bits (zero pivot, root fallback, a NaN or an
+    infinity read by a pivot test), plus ST_NONFINITE when a compressed rule
+    reads a non-finite A21 entry while building C (compression reads all of
+    A21; restricted pivoting never reads A21, TPP reads it through its
+    tests).
     """
     if method not in METHODS:
         raise ValueError(method)
@@ -230,7 +236,10 @@ def factor_supernode(A, p, method="relaxed", u=0.01, small=1e-20, forced=None, r
         L21, W, A21d = solve_a21(A21P, L, piv, d, nelim)
         out[p:, :nelim] = L21
         out[p:, nelim:] = A21d
-    return SupernodeFactors(out, perm, piv, d, nelim, W, C, crow, trap.log, trap)
+    status = trap.status
+    if method in ("strict", "relaxed") and A21.dtype != object and not np.isfinite(A21).all():
+        status |= ST_NONFINITE
+    return SupernodeFactors(out, perm, piv, d, nelim, W, C, crow, trap.log, trap, status)
 
 
 # ---------------------------------------------------------------------------

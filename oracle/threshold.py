@@ -88,6 +88,11 @@ PIV_2X2_FIRST = 2   # first column of a 2x2 pivot
 PIV_2X2_SECOND = -2  # second column of a 2x2 pivot
 PIV_DELAYED = -1    # not eliminated (delayed to a later supernode)
 
+# Status bits (the same meaning as the library's device status word).
+ST_ZERO_PIVOT = 1      # a zero pivot was recorded
+ST_NONFINITE = 2       # a NaN or an infinity was read by a pivot test
+ST_ROOT_FALLBACK = 8   # a root panel eliminated a column regardless of u
+
 # Update rules for the bottom block R.
 R_NORMAL = "normal"   # eq. (4.3): TPP, relaxed
 R_ABS = "abs"         # eq. (4.4): strict
@@ -110,6 +115,15 @@ def _absmax(x, zero):
     if x.size == 0:
         return zero
     return np.max(np.abs(x))
+
+
+def _finite(x):
+    """True when every entry of x (a scalar or an array) is a finite number;
+    exact rationals always are."""
+    x = np.asarray(x)
+    if x.dtype == object:
+        return True
+    return bool(np.isfinite(x).all())
 
 
 def _ratio_margin(value, bound):
@@ -156,6 +170,7 @@ class TrapezoidFactors:
            of a 2x2 pivot, else 0.
     nelim: number of eliminated columns.
     log:   list of Decision.
+    status: OR of the ST_* bits.
     """
     T: np.ndarray
     R: np.ndarray
@@ -164,6 +179,7 @@ class TrapezoidFactors:
     d: np.ndarray
     nelim: int
     log: list
+    status: int = 0
 
     def fragile_steps(self, tol=FRAGILE):
         return [i for i, dec in enumerate(self.log) if dec.fragile(tol)]
@@ -328,9 +344,11 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
     d = np.full(2 * p, zero, dtype=T.dtype) if p else np.zeros(0, dtype=T.dtype)
     log = []
     nelim = 0
+    status = 0
 
     def record_zero(m):
-        nonlocal nelim
+        nonlocal nelim, status
+        status |= ST_ZERO_PIVOT
         _swap(T, R, perm, m, nelim)
         k = nelim
         piv[k] = PIV_ZERO
@@ -382,9 +400,11 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
                 record_zero(pos[0])
             else:
                 raise ValueError(dec)
-        return TrapezoidFactors(T, R, perm, piv, d, nelim, log)
+        return TrapezoidFactors(T, R, perm, piv, d, nelim, log, status)
 
     def fallback_step():
+        nonlocal status
+        status |= ST_ROOT_FALLBACK
         k = nelim
         if abs(T[k, k]) >= small:
             log.append(Decision("fallback", (int(perm[k]),), (k,), nelim))
@@ -412,7 +432,10 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
             log.append(Decision("pass", (), (m,), nelim))
             continue
         # Zero column: everything in the uneliminated column is below small.
-        colmax = max(abs(T[m, m]), _absmax(_col_values(T, R, nelim, m, {m}), zero))
+        colm = _col_values(T, R, nelim, m, {m})
+        if not (_finite(T[m, m]) and _finite(colm)):
+            status |= ST_NONFINITE
+        colmax = max(abs(T[m, m]), _absmax(colm, zero))
         if colmax < small:
             log.append(Decision("zero", (int(perm[m]),), (m,), nelim,
                                 {"zero": -_ratio_margin(colmax, small)}))
@@ -424,6 +447,8 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
             # Partner t: largest |a(m, j)| over the pending columns nelim..m-1.
             row = np.abs(T[m, nelim:m])
             t = nelim + int(np.argmax(row))
+            if not (_finite(row) and _finite(T[t, t]) and _finite(_col_values(T, R, nelim, t, {t}))):
+                status |= ST_NONFINITE
             margins = {}
             if row.size > 1:
                 srt = sorted((float(v) for v in row), reverse=True)
@@ -455,4 +480,4 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
             continue
         log.append(Decision("reject", (int(perm[m]),), (m,), nelim, {**tried2, **mg}, vals))
         m += 1
-    return TrapezoidFactors(T, R, perm, piv, d, nelim, log)
+    return TrapezoidFactors(T, R, perm, piv, d, nelim, log, status)
