@@ -77,7 +77,7 @@ extern "C" {
 
 /* Device status bits. */
 #define CTP_STATUS_ZERO_PIVOT 1     /* a zero pivot was recorded */
-#define CTP_STATUS_NONFINITE 2      /* a NaN/Inf reached a pivot test */
+#define CTP_STATUS_NONFINITE 2      /* a NaN/Inf was read by a pivot test or by the compression */
 #define CTP_STATUS_RELAXED_RESCAN 4 /* relaxed C needed a full column rescan */
 #define CTP_STATUS_ROOT_FALLBACK 8  /* CTP_FLAG_ROOT: a column was eliminated regardless of u */
 
@@ -87,7 +87,7 @@ extern "C" {
                               position nelim regardless of u: 1x1 unless below
                               small, else a 2x2 with the next column if its
                               determinant is safely nonzero, else a zero pivot) */
-#define CTP_FLAG_S_TILED 4u /* batches: each node's S is stored as the 128 x 128 tiles of
+#define CTP_FLAG_S_TILED 4u /* ctp_supernode and batches: S is stored as the 128 x 128 tiles of
                               its lower triangle, tile t = tm (tm + 1) / 2 + tn (tn <= tm)
                               at s + s_off + t * 16384, each column-major with ld 128
                               (rows past n - p of edge tiles are not written) */
@@ -101,6 +101,7 @@ extern "C" {
 
 #define CTP_ERR_HIP_BASE (-1000)
 #define CTP_ERR_PANEL_TOO_WIDE (-900)  /* dense: delays grew a panel past CTP_MAX_P */
+
 
 /* Largest p supported by the single-workgroup pivot search and the solve. */
 #define CTP_MAX_P 512
@@ -188,11 +189,22 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm,
                         const ctp_opts* opts, void* work, size_t lwork,
                         hipStream_t stream);
 
-/* Factor + Solve in one call (ctp_factor_supernode then
- * ctp_solve_supernode, for every rule). */
+/* Factor, Solve and Form in one call (Section 1's three tasks on one
+ * supernode; Fig. 4.1 (a)-(e) for the compressed rules): ctp_factor_supernode,
+ * ctp_solve_supernode, then, when s is not NULL, the whole lower triangle of
+ * S = L21 D11 L21^T (order n-p) in one launch:
+ *   default:          column-major, entry (i, j), j <= i, at s[i + j*lds],
+ *                     lds >= n-p; entries above the diagonal are not written;
+ *   CTP_FLAG_S_TILED: the packed 128 x 128 tiles of the lower triangle, tile
+ *                     (tm, tn), tn <= tm, at s + 16384 (tm (tm+1)/2 + tn),
+ *                     column-major with ld 128 (lds ignored; rows and
+ *                     columns past n-p of edge tiles are not written).
+ * s = NULL: Factor and Solve only.  Arguments otherwise as for
+ * ctp_factor_supernode.  Errors: -12 lds too small, -13 workspace too
+ * small, others as for the three steps. */
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
                   int* perm, int* piv, double* d, int* nelim, int* status,
-                  void* work, size_t lwork, hipStream_t stream);
+                  double* s, int lds, void* work, size_t lwork, hipStream_t stream);
 
 /* Form task (Section 1): rows row0..row0+nrows-1 of the lower triangle of
  * S = L21 D11 L21^T, S of order n-p indexed like the rows of A21.  Entry
@@ -253,10 +265,32 @@ int ctp_batch_plan(int count, ctp_node* nodes, const ctp_opts* opts, ctp_batch_i
  * place, as ctp_supernode); s: the S buffer (may be NULL); perm, piv, d:
  * outputs at each node's out_off; nelim[count], status[count]: device
  * outputs per node.  work: info->work_bytes bytes.  No host
- * synchronization, no allocation. */
+ * synchronization, no allocation.  The same as the three calls below in
+ * order on one workspace. */
 int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
                           double* s, int* perm, int* piv, double* d, int* nelim, int* status,
                           const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream);
+
+/* The three tasks of a batch one at a time (Section 1: Factor, Solve,
+ * Form of every node).  Factor: compression (steps 1-2 above) and pivot
+ * search of every node, outputs as for ctp_supernode_batched (status and
+ * nelim cleared first).  Solve: L21 and the delayed columns of every node
+ * from the factorization's perm, piv, d and nelim, leaving each node's
+ * W = L21 D in its part of the workspace.  Form: S of every node with
+ * s_off >= 0 (opts->flags CTP_FLAG_S_TILED / CTP_FLAG_S_SUBTRACT as for
+ * ctp_supernode_batched) from the panels and the W the Solve left.  The
+ * three calls take the same nodes, info and workspace; between them the
+ * workspace must not be changed.  Errors as ctp_supernode_batched (-5: a
+ * missing perm for the Solve or s for the Form). */
+int ctp_factor_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                                 int* perm, int* piv, double* d, int* nelim, int* status, const ctp_opts* opts,
+                                 void* work, size_t lwork, hipStream_t stream);
+int ctp_solve_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                                const int* perm, const int* piv, const double* d, const int* nelim,
+                                const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream);
+int ctp_schur_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, const double* panels,
+                      const int* piv, const double* d, const int* nelim, double* s, const ctp_opts* opts,
+                      void* work, size_t lwork, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Dense symmetric indefinite LDL^T from supernode panels (Section 1: the

@@ -20,6 +20,8 @@ int launch_schur(int n, int p, const double* a, int lda, const int* piv, const d
 int launch_schur_w(int n, int p, const double* a, int lda, const double* w, int ldw,
                    const int* nelim, int row0, int nrows, double* s, int lds, int variant,
                    hipStream_t stream);
+int launch_schur_full(int n, int p, const double* a, int lda, const double* w, int ldw, const int* nelim,
+                      double* s, int lds, int tiled, int workgroups, hipStream_t stream);
 int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
                   const int* nelim, double* w, int ldw, hipStream_t stream);
 
@@ -27,7 +29,7 @@ size_t batch_header_bytes(int count);
 int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags, double u, double small,
                        double* panels, double* s, int* perm, int* piv, double* d, int* nelim, int* status,
                        void* work, BatchNode** nodes_out, void** pargs_out, unsigned int** counter_out,
-                       hipStream_t stream);
+                       int reset, hipStream_t stream);
 int launch_compress_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int max_chunks,
                           hipStream_t stream);
 int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipStream_t stream);
@@ -158,10 +160,19 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const
 }
 
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
-                  double* d, int* nelim, int* status, void* work, size_t lwork, hipStream_t stream) {
+                  double* d, int* nelim, int* status, double* s, int lds, void* work, size_t lwork,
+                  hipStream_t stream) {
+  const int r = n - p;
+  const bool tiled = opts && (opts->flags & CTP_FLAG_S_TILED);
+  if (s && !tiled && lds < (r > 1 ? r : 1)) return -12;
   int rc = ctp_factor_supernode(n, p, a, lda, opts, perm, piv, d, nelim, status, work, lwork, stream);
-  if (rc) return rc;
-  return ctp_solve_supernode(n, p, a, lda, perm, piv, d, nelim, opts, work, lwork, stream);
+  if (rc) return rc == -12 ? -13 : rc;
+  rc = ctp_solve_supernode(n, p, a, lda, perm, piv, d, nelim, opts, work, lwork, stream);
+  if (rc) return rc == -11 ? -13 : rc;
+  if (!s || r <= 0 || p == 0) return 0;
+  Workspace ws = workspace_layout(n, p, opts->method);
+  const double* w = reinterpret_cast<const double*>(static_cast<const unsigned char*>(work) + ws.w_off);
+  return launch_schur_full(n, p, a, lda, w, ws.ldw, nelim, s, lds, tiled ? 1 : 0, 0, stream);
 }
 
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
@@ -228,35 +239,104 @@ int ctp_batch_plan(int count, ctp_node* nodes, const ctp_opts* opts, ctp_batch_i
   return 0;
 }
 
-int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
-                          double* s, int* perm, int* piv, double* d, int* nelim, int* status,
-                          const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream) {
+// The batched calls share one argument check; `need` says which pointers the
+// call uses (1: factor outputs, 2: nelim / piv / d read back, 4: S).
+static int batch_check(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels, double* s,
+                       int* perm, int* piv, double* d, int* nelim, int* status, const ctp_opts* opts, void* work,
+                       size_t lwork, int need) {
   if (count < 0) return -1;
   if (count > 0 && !nodes) return -2;
   if (!info || info->count != count) return -3;
-  if (count > 0 && (!panels || !perm || !piv || !d || !nelim || !status)) return -4;
+  if (count > 0 && !panels) return -4;
+  if (count > 0 && (need & 1) && (!perm || !status)) return -4;
+  if (count > 0 && (!piv || !d || !nelim)) return -4;
+  if (count > 0 && (need & 4) && !s) return -5;
   if (check_opts(opts) || opts->method == CTP_TPP) return -11;
   if ((opts->flags & CTP_FLAG_S_SUBTRACT) && (opts->flags & CTP_FLAG_S_TILED)) return -11;
   if (!work || lwork < info->work_bytes) return -12;
-  if (count == 0) return 0;
+  return 0;
+}
+
+struct BatchLaunch {
   BatchNode* bn = nullptr;
   void* pargs = nullptr;
   unsigned int* counter = nullptr;
+};
+
+static int batch_factor(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels, double* s,
+                        int* perm, int* piv, double* d, int* nelim, int* status, const ctp_opts* opts, void* work,
+                        BatchLaunch& L, hipStream_t stream) {
   int rc = launch_batch_setup(count, nodes, opts->method, opts->flags, opts->u, opts->small, panels, s, perm, piv,
-                              d, nelim, status, work, &bn, &pargs, &counter, stream);
+                              d, nelim, status, work, &L.bn, &L.pargs, &L.counter, 1, stream);
   if (rc) return rc;
-  rc = launch_compress_batch(count, bn, opts->method, info->max_p, info->max_r, info->max_chunks, stream);
+  rc = launch_compress_batch(count, L.bn, opts->method, info->max_p, info->max_r, info->max_chunks, stream);
   if (rc) return rc;
   const int rrows = opts->method == CTP_RESTRICTED ? 0 : info->max_p;
-  rc = launch_pivot_batch(count, pargs, info->max_p, rrows, stream);
+  return launch_pivot_batch(count, L.pargs, info->max_p, rrows, stream);
+}
+
+static int batch_form(int count, const ctp_batch_info* info, double* s, const ctp_opts* opts, BatchLaunch& L,
+                      hipStream_t stream) {
+  if (!s || info->tiles <= 0) return 0;
+  return launch_schur_batch(count, L.bn, opts->method, info->tiles, (opts->flags & CTP_FLAG_S_TILED) ? 1 : 0,
+                            (opts->flags & CTP_FLAG_S_SUBTRACT) ? 1 : 0, L.counter, opts->tile,
+                            info->form_workgroups, stream);
+}
+
+int ctp_factor_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                                 int* perm, int* piv, double* d, int* nelim, int* status, const ctp_opts* opts,
+                                 void* work, size_t lwork, hipStream_t stream) {
+  int rc = batch_check(count, nodes, info, panels, nullptr, perm, piv, d, nelim, status, opts, work, lwork, 1);
+  if (rc || count == 0) return rc;
+  BatchLaunch L;
+  return batch_factor(count, nodes, info, panels, nullptr, perm, piv, d, nelim, status, opts, work, L, stream);
+}
+
+int ctp_solve_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                                const int* perm, const int* piv, const double* d, const int* nelim,
+                                const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream) {
+  int* pm = const_cast<int*>(perm);
+  int* pv = const_cast<int*>(piv);
+  double* dd = const_cast<double*>(d);
+  int* ne = const_cast<int*>(nelim);
+  int rc = batch_check(count, nodes, info, panels, nullptr, pm, pv, dd, ne, nullptr, opts, work, lwork, 2);
+  if (rc || count == 0) return rc;
+  if (!perm) return -5;
+  BatchLaunch L;
+  // descriptors only: the factorization's outputs stay as they are
+  rc = launch_batch_setup(count, nodes, opts->method, opts->flags, opts->u, opts->small, panels, nullptr, pm, pv, dd,
+                          ne, ne, work, &L.bn, &L.pargs, &L.counter, 0, stream);
   if (rc) return rc;
-  rc = launch_solve_batch(count, bn, opts->method, info->max_p, info->max_r, stream);
+  return launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, stream);
+}
+
+int ctp_schur_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, const double* panels,
+                      const int* piv, const double* d, const int* nelim, double* s, const ctp_opts* opts,
+                      void* work, size_t lwork, hipStream_t stream) {
+  double* pa = const_cast<double*>(panels);
+  int* pv = const_cast<int*>(piv);
+  double* dd = const_cast<double*>(d);
+  int* ne = const_cast<int*>(nelim);
+  int rc = batch_check(count, nodes, info, pa, s, nullptr, pv, dd, ne, nullptr, opts, work, lwork, 2 | 4);
+  if (rc || count == 0) return rc;
+  BatchLaunch L;
+  rc = launch_batch_setup(count, nodes, opts->method, opts->flags, opts->u, opts->small, pa, s, pv, pv, dd, ne, ne,
+                          work, &L.bn, &L.pargs, &L.counter, 0, stream);
   if (rc) return rc;
-  if (s && info->tiles > 0)
-    rc = launch_schur_batch(count, bn, opts->method, info->tiles, (opts->flags & CTP_FLAG_S_TILED) ? 1 : 0,
-                            (opts->flags & CTP_FLAG_S_SUBTRACT) ? 1 : 0, counter,
-                            opts->tile, info->form_workgroups, stream);
-  return rc;
+  return batch_form(count, info, s, opts, L, stream);
+}
+
+int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, double* panels,
+                          double* s, int* perm, int* piv, double* d, int* nelim, int* status,
+                          const ctp_opts* opts, void* work, size_t lwork, hipStream_t stream) {
+  int rc = batch_check(count, nodes, info, panels, nullptr, perm, piv, d, nelim, status, opts, work, lwork, 1);
+  if (rc || count == 0) return rc;
+  BatchLaunch L;
+  rc = batch_factor(count, nodes, info, panels, s, perm, piv, d, nelim, status, opts, work, L, stream);
+  if (rc) return rc;
+  rc = launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, stream);
+  if (rc) return rc;
+  return batch_form(count, info, s, opts, L, stream);
 }
 
 }  // extern "C"

@@ -675,7 +675,7 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
     if (lowp && width > carried)
       dense_from_f32_kernel<<<dim3(4, width - carried), 256, 0, stream>>>(a, lda, w32, L.ld32, k0 + carried, N);
     po.flags = opts->flags | (root ? CTP_FLAG_ROOT : 0u);
-    rc = ctp_supernode(n, width, ap, lda, &po, pperm, ppiv, pd, pnelim, pstatus, sn, L.sn_bytes, stream);
+    rc = ctp_supernode(n, width, ap, lda, &po, pperm, ppiv, pd, pnelim, pstatus, nullptr, 0, sn, L.sn_bytes, stream);
     if (rc) return rc;
     if (k0 > 0) dense_perm_left_kernel<<<k0, 256, 0, stream>>>(a, lda, k0, width, pperm);
     dense_bookkeep_kernel<<<1, 512, 0, stream>>>(k0, width, pperm, ppiv, pd, pnelim, perm, piv, d);

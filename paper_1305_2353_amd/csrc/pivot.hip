@@ -242,12 +242,17 @@ CTP_DEV void for_r_rows(int rc, int r, F&& f) {
 
 struct Top2 {
   double v1, v2;
+  bool bad;   // this thread met a NaN or an infinity (reported in the status word)
 };
 
-CTP_DEV Top2 top2_empty() { return Top2{-1.0, -1.0}; }
+CTP_DEV Top2 top2_empty() { return Top2{-1.0, -1.0, false}; }
 
-// x = |a| or NaN; a NaN never enters
+// true for NaN and +-infinity
+CTP_DEV bool nonfinite(double x) { return !(fabs(x) <= 1.7976931348623157e308); }
+
+// x = |a| or NaN; a NaN never enters the maxima
 CTP_DEV void top2_insert(Top2& t, double x) {
+  t.bad |= nonfinite(x);
   x = fmax(x, -1.0);
   t.v2 = fmax(t.v2, fmin(t.v1, x));
   t.v1 = fmax(t.v1, x);
@@ -589,7 +594,7 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
         action = ACT_ZERO;
         mc = k;
       }
-      if (threadIdx.x == 0) pv_sh.status |= ST_ROOT_FALLBACK;
+      if (threadIdx.x == 0) atomicOr(&pv_sh.status, ST_ROOT_FALLBACK);
       // every thread has read the block before its owners overwrite it
       __syncthreads();
     } else {
@@ -605,19 +610,24 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
       int ri = 0x7fffffff;
       for (int j = jp; j < m; j += NT) {
         double x = fabs(j == jp ? lazy_a_from(g, ns, m, j, xp) : lazy_a(g, ns, m, j));
+        cm.bad |= nonfinite(x);
         if (x != x) x = -0.5;   // NaN: loses to any number, keeps t a valid index
         if (x > rv) {
           rv = x;
           ri = j;
         }
       }
-      if (threadIdx.x == 0) pv_sh.sc[slot][0] = lazy_a_from(g, ns, m, m, xd);
+      if (threadIdx.x == 0) {
+        const double v = lazy_a_from(g, ns, m, m, xd);
+        pv_sh.sc[slot][0] = v;
+        cm.bad |= nonfinite(v);
+      }
+      if (cm.bad) atomicOr(&pv_sh.status, ST_NONFINITE);
       reduce_pass<NT, true>(cm, rv, ri, slot);
       const double amm = pv_sh.sc[slot][0];
       slot ^= 1;
       const double maxm = top2_max(cm);
       const double colmax = fmax(fabs(amm), maxm);
-      if (threadIdx.x == 0 && !isfinite(colmax)) pv_sh.status |= ST_NONFINITE;
       if (colmax < g.small) {
         action = ACT_ZERO;
       } else if (m > nelim) {
@@ -630,9 +640,12 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
         Top2 ct = top2_empty();
         col_scan<NT>(g, ns, rc, nelim, t, cB, qb, ct);
         if (threadIdx.x == 0) {
-          pv_sh.sc[slot][0] = lazy_a_from(g, ns, t, t, xtt);
+          const double v = lazy_a_from(g, ns, t, t, xtt);
+          pv_sh.sc[slot][0] = v;
           pv_sh.sc[slot][2] = pv_dyn[cA + t];
+          ct.bad |= nonfinite(v);
         }
+        if (ct.bad) atomicOr(&pv_sh.status, ST_NONFINITE);
         if (threadIdx.x == (m - nelim) % NT) pv_sh.sc[slot][1] = pv_dyn[cB + m];
         double dv = -1.0;
         int di = 0;
@@ -790,7 +803,7 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
         pv_piv[k] = PIV_ZERO;
         pv_d[2 * k] = 0.0;
         pv_d[2 * k + 1] = 0.0;
-        pv_sh.status |= ST_ZERO_PIVOT;
+        atomicOr(&pv_sh.status, ST_ZERO_PIVOT);
       } else if (!two) {
         pv_piv[k] = PIV_1X1;
         pv_d[2 * k] = d1;
@@ -1030,7 +1043,7 @@ size_t pivot_lds_bytes(int p, int r);
 __global__ void batch_setup_kernel(const ctp_node* __restrict__ in, int count, int method, unsigned flags,
                                    double u, double small, double* panels, double* s, int* perm, int* piv,
                                    double* d, int* nelim, int* status, unsigned char* work,
-                                   BatchNode* __restrict__ nodes, PivotArgs* __restrict__ pargs) {
+                                   BatchNode* __restrict__ nodes, PivotArgs* __restrict__ pargs, int reset) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const ctp_node c = in[i];
@@ -1053,8 +1066,10 @@ __global__ void batch_setup_kernel(const ctp_node* __restrict__ in, int count, i
   nd.status = status + i;
   nd.work = work + c.work_off;
   nodes[i] = nd;
-  status[i] = 0;
-  nelim[i] = 0;
+  if (reset) {
+    status[i] = 0;
+    nelim[i] = 0;
+  }
   const Workspace ws = workspace_layout(c.n, c.p, method);
   PivotArgs g;
   g.p = c.p;
@@ -1091,14 +1106,14 @@ size_t batch_header_bytes(int count) {
 int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags, double u, double small,
                        double* panels, double* s, int* perm, int* piv, double* d, int* nelim, int* status,
                        void* work, BatchNode** nodes_out, void** pargs_out, unsigned int** counter_out,
-                       hipStream_t stream) {
+                       int reset, hipStream_t stream) {
   unsigned char* base = static_cast<unsigned char*>(work);
   BatchNode* nodes = reinterpret_cast<BatchNode*>(base);
   PivotArgs* pargs = reinterpret_cast<PivotArgs*>(base + align_up((size_t)count * sizeof(BatchNode), 256));
   unsigned int* counter = reinterpret_cast<unsigned int*>(
       base + align_up((size_t)count * sizeof(BatchNode), 256) + align_up((size_t)count * sizeof(PivotArgs), 256));
   batch_setup_kernel<<<(count + 127) / 128, 128, 0, stream>>>(in, count, method, flags, u, small, panels, s, perm,
-                                                             piv, d, nelim, status, base, nodes, pargs);
+                                                             piv, d, nelim, status, base, nodes, pargs, reset);
   *nodes_out = nodes;
   *pargs_out = pargs;
   *counter_out = counter;

@@ -702,6 +702,104 @@ int launch_schur_batch(int count, const BatchNode* nodes, int method, long long 
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
 
+// ---------------------------------------------------------------------------
+// Whole lower triangle of one node's S in one persistent launch (the Form
+// of the fused supernode call).  Tiles are numbered in groups of SC_GROUP
+// tile rows; inside a group column by column (the tiles of one column of
+// the group share the W block, the group's rows share their L21 blocks), so
+// consecutive numbers reuse operands.  The numbers are cut into SC_NXCD
+// contiguous ranges, one per XCD (workgroup b runs on XCD b mod SC_NXCD),
+// and the workgroups of an XCD stride through its range together.  Output:
+// column-major S (ld lds) or, with tiled, the packed 128 x 128 tiles of the
+// lower triangle, tile tm (tm + 1) / 2 + tn at s + 16384 t (ld 128).
+// ---------------------------------------------------------------------------
+
+// tiles before group G, every earlier group being full: sum over the
+// SC_GROUP G rows before it of (tm + 1) = 32 G^2 + 4 G for SC_GROUP = 8
+CTP_DEV long long sc_group_start(long long G) { return 32 * G * G + 4 * G; }
+
+CTP_DEV void sc_persist_tile(long long t, int ntm, int& tm, int& tn) {
+  long long G = (long long)((sqrt(16.0 + 128.0 * (double)t) - 4.0) / 64.0);
+  while (sc_group_start(G + 1) <= t) ++G;
+  while (G > 0 && sc_group_start(G) > t) --G;
+  long long l = t - sc_group_start(G);
+  const int r0 = (int)(G * SC_GROUP);
+  const int gm = min(SC_GROUP, ntm - r0);
+  const long long full = (long long)gm * (r0 + 1);   // columns tn <= r0 hold gm tiles each
+  if (l < full) {
+    tn = (int)(l / gm);
+    tm = r0 + (int)(l % gm);
+    return;
+  }
+  l -= full;
+  int c = 1;
+  while (l >= gm - c) {
+    l -= gm - c;
+    ++c;
+  }
+  tn = r0 + c;
+  tm = r0 + c + (int)l;
+}
+
+template <int VAR>
+__global__ __launch_bounds__(SC_THREADS, 2) void schur_persist_kernel(SchurWArgs g, long long total, int per_x,
+                                                                     int aligned) {
+  const int x = blockIdx.x % SC_NXCD, w = blockIdx.x / SC_NXCD;
+  const long long per = (total + SC_NXCD - 1) / SC_NXCD;
+  const long long t0 = (long long)x * per;
+  const long long t1 = min(total, t0 + per);
+  const int K = min(max(*g.nelim_p, 0), g.p);
+  double* const base = g.s;
+  for (long long t = t0 + w; t < t1; t += per_x) {
+    int tm, tn;
+    sc_persist_tile(t, g.ntm, tm, tn);
+    const int i0 = tm * SC_BM, j0 = tn * SC_BN;
+    SchurWArgs h = g;
+    if (g.tiled) h.s = base + ((long long)tm * (tm + 1) / 2 + tn) * (SC_BM * SC_BN);
+    if (aligned && i0 + SC_BM <= g.r && j0 + SC_BN <= g.r) schur_w_tile<true, VAR>(h, i0, j0, K, sc_dyn);
+    else schur_w_tile<false, VAR>(h, i0, j0, K, sc_dyn);
+    __syncthreads();   // LDS is reused by the next tile
+  }
+}
+
+// Whole lower triangle of S = L21 W^T: column-major (lds) or packed tiles.
+int launch_schur_full(int n, int p, const double* a, int lda, const double* w, int ldw, const int* nelim,
+                      double* s, int lds, int tiled, int workgroups, hipStream_t stream) {
+  SchurWArgs g;
+  g.r = n - p;
+  g.l21 = a + p;
+  g.lda = lda;
+  g.w = w;
+  g.ldw = ldw;
+  g.nelim_p = nelim;
+  g.p = p;
+  g.row0 = 0;
+  g.nrows = g.r;
+  g.s = s;
+  g.lds = tiled ? SC_BM : lds;
+  g.tiled = tiled;
+  g.ntm = (g.r + SC_BM - 1) / SC_BM;
+  g.ntn = g.ntm;
+  g.per_xcd = 0;
+  const long long total = (long long)g.ntm * (g.ntm + 1) / 2;
+  if (total == 0 || p == 0) return 0;
+  const int aligned = ((reinterpret_cast<uintptr_t>(a + p) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&
+                      lda % 2 == 0 && ldw % 2 == 0;
+  long long nwg = workgroups > 0 ? workgroups : 512;
+  nwg = std::min<long long>(nwg, (total + SC_NXCD - 1) / SC_NXCD * SC_NXCD);
+  nwg = (nwg + SC_NXCD - 1) / SC_NXCD * SC_NXCD;
+  constexpr int VAR = 305;
+  constexpr int bytes = SchurWShape<VAR>::LDS_BYTES;
+  if (bytes > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(schur_persist_kernel<VAR>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  }
+  schur_persist_kernel<VAR><<<(unsigned)nwg, SC_THREADS, bytes, stream>>>(g, total, (int)(nwg / SC_NXCD), aligned);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
 // C(i, j) -= sum_k L21(i, k) W(j, k) for the lower triangle i >= j of the
 // order-(n-p) matrix C (column-major, ldc): the trailing update of a
 // right-looking factorization, rows of L21 = rows p..n-1 of the panel.

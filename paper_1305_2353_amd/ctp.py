@@ -28,15 +28,17 @@ CTP_FLAG_ROOT = 1
 CTP_FLAG_ONE_WG = 2
 CTP_FLAG_S_TILED = 4
 SC_TILE = 128
+CTP_FLAG_S_SUBTRACT = 8
 CTP_ERR_PANEL_TOO_WIDE = -900
 PREC_IDS = {"fp64": 0, "fp32": 1, "bf16": 2}
 CTP_MAX_P = 512
 
 # Every symbol declared in include/ctp.h.
 EXPORTED = ("ctp_default_opts", "ctp_version", "ctp_workspace_size", "ctp_compress",
-            "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode", "ctp_schur",
-            "ctp_dense_workspace_size", "ctp_ldlt_dense", "ctp_ldlt_solve", "ctp_ldlt_refine",
-            "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched",
+            "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode",
+            "ctp_schur", "ctp_dense_workspace_size", "ctp_ldlt_dense", "ctp_ldlt_solve", "ctp_ldlt_refine",
+            "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched", "ctp_factor_supernode_batched",
+            "ctp_solve_supernode_batched", "ctp_schur_batched",
             "ctp_dense_batched_workspace_size", "ctp_ldlt_dense_batched", "ctp_ldlt_solve_batched",
             "ctp_ldlt_adjoint_batched")
 
@@ -82,7 +84,7 @@ def load(path=LIB_PATH):
         "ctp_compress": (I, [I, I, P, I, I, P, I, P, P, P, SZ, P]),
         "ctp_factor_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
         "ctp_solve_supernode": (I, [I, I, P, I, P, P, P, P, OPT, P, SZ, P]),
-        "ctp_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
+        "ctp_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, I, P, SZ, P]),
         "ctp_schur": (I, [I, I, P, I, P, P, P, I, I, P, I, OPT, P, SZ, P]),
         "ctp_dense_workspace_size": (I, [I, I, OPT, I, ctypes.POINTER(SZ)]),
         "ctp_ldlt_dense": (I, [I, I, P, I, OPT, P, P, P, P, ctypes.POINTER(I), P, SZ, P]),
@@ -92,6 +94,10 @@ def load(path=LIB_PATH):
         "ctp_ldlt_adjoint": (I, [I, I, P, I, P, P, P, P, I, P, I, P, I, OPT, I, P, SZ, P]),
         "ctp_batch_plan": (I, [I, P, OPT, ctypes.POINTER(CtpBatchInfo)]),
         "ctp_supernode_batched": (I, [I, P, ctypes.POINTER(CtpBatchInfo), P, P, P, P, P, P, P, OPT, P, SZ, P]),
+        "ctp_factor_supernode_batched": (I, [I, P, ctypes.POINTER(CtpBatchInfo), P, P, P, P, P, P, OPT, P, SZ,
+                                             P]),
+        "ctp_solve_supernode_batched": (I, [I, P, ctypes.POINTER(CtpBatchInfo), P, P, P, P, P, OPT, P, SZ, P]),
+        "ctp_schur_batched": (I, [I, P, ctypes.POINTER(CtpBatchInfo), P, P, P, P, P, OPT, P, SZ, P]),
         "ctp_dense_batched_workspace_size": (I, [I, I, I, OPT, ctypes.POINTER(SZ)]),
         "ctp_ldlt_dense_batched": (I, [I, I, I, P, I, LL, OPT, P, P, P, P, ctypes.POINTER(I), P, SZ, P]),
         "ctp_ldlt_solve_batched": (I, [I, I, I, P, I, LL, P, P, P, P, I, LL, OPT, I, P, SZ, P]),
@@ -209,13 +215,38 @@ def ctp_solve_supernode(a, f, opts, work=None):
            "ctp_solve_supernode")
 
 
-def ctp_supernode(a, opts, work=None, outs=None):
-    """Factor + Solve in place; returns the factor dict."""
+def _s_args(s, r, opts):
+    """Pointer and leading dimension of an S argument of ctp_supernode: a
+    column-major (r x r) float64 tensor, or with CTP_FLAG_S_TILED a flat
+    buffer of s_tiles(r) * 16384 doubles; None for no Form."""
+    if s is None:
+        return ctypes.c_void_p(0), max(r, 1)
+    if s.dtype != torch.float64 or not s.is_cuda:
+        raise CtpError("S must be a float64 CUDA tensor")
+    if opts.flags & CTP_FLAG_S_TILED:
+        if s.numel() < s_tiles(r) * SC_TILE * SC_TILE:
+            raise CtpError("tiled S buffer too small")
+        return _ptr(s), SC_TILE
+    if s.dim() != 2 or tuple(s.shape) != (r, r) or (r > 1 and s.stride(0) != 1):
+        raise CtpError("S must be a column-major (n-p) x (n-p) tensor")
+    return _ptr(s), max(s.stride(1) if r > 1 else 1, r, 1)
+
+
+def s_tiles(r):
+    """Number of 128 x 128 tiles of the lower triangle of an order-r S."""
+    nt = (r + SC_TILE - 1) // SC_TILE
+    return nt * (nt + 1) // 2
+
+
+def ctp_supernode(a, opts, work=None, outs=None, s=None):
+    """Factor + Solve in place, and with s the whole lower triangle of S
+    (Form) into s; returns the factor dict."""
     n, p, lda = _panel_args(a)
     work = work if work is not None else workspace(n, p, opts, a.device)
     perm, piv, d, nelim, status = outs if outs is not None else _outputs(p, a.device)
+    sp, lds = _s_args(s, n - p, opts)
     _check(load().ctp_supernode(n, p, _ptr(a), lda, ctypes.byref(opts), _ptr(perm), _ptr(piv), _ptr(d),
-                                _ptr(nelim), _ptr(status), _ptr(work), work.numel(), _stream()),
+                                _ptr(nelim), _ptr(status), sp, lds, _ptr(work), work.numel(), _stream()),
            "ctp_supernode")
     return {"perm": perm[:p], "piv": piv[:p], "d": d[:2 * p], "nelim": nelim, "status": status}
 
@@ -489,3 +520,25 @@ class Batch:
                                             _ptr(self.nelim), _ptr(self.status), ctypes.byref(self.opts),
                                             _ptr(self.work), self.work.numel(), _stream()),
                "ctp_supernode_batched")
+
+    def factor(self):
+        """Factor task of every node (ctp_factor_supernode_batched)."""
+        _check(load().ctp_factor_supernode_batched(self.count, _ptr(self.nodes), ctypes.byref(self.info),
+                                                   _ptr(self.panels), _ptr(self.perm), _ptr(self.piv), _ptr(self.d),
+                                                   _ptr(self.nelim), _ptr(self.status), ctypes.byref(self.opts),
+                                                   _ptr(self.work), self.work.numel(), _stream()),
+               "ctp_factor_supernode_batched")
+
+    def solve(self):
+        """Solve task of every node (ctp_solve_supernode_batched)."""
+        _check(load().ctp_solve_supernode_batched(self.count, _ptr(self.nodes), ctypes.byref(self.info),
+                                                  _ptr(self.panels), _ptr(self.perm), _ptr(self.piv), _ptr(self.d),
+                                                  _ptr(self.nelim), ctypes.byref(self.opts), _ptr(self.work),
+                                                  self.work.numel(), _stream()), "ctp_solve_supernode_batched")
+
+    def schur(self):
+        """Form task of every node with S (ctp_schur_batched)."""
+        _check(load().ctp_schur_batched(self.count, _ptr(self.nodes), ctypes.byref(self.info), _ptr(self.panels),
+                                        _ptr(self.piv), _ptr(self.d), _ptr(self.nelim), _ptr(self.S),
+                                        ctypes.byref(self.opts), _ptr(self.work), self.work.numel(), _stream()),
+               "ctp_schur_batched")

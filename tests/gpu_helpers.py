@@ -52,11 +52,11 @@ def rel_err(x, ref):
     return float(np.abs(x - ref).max() / max(1.0, np.abs(ref).max()))
 
 
-def run_supernode(A, p, method, u=0.01, small=1e-20, schur=True, lda=None):
+def run_supernode(A, p, method, u=0.01, small=1e-20, schur=True, lda=None, flags=0):
     """Factor + Solve (+ the whole S) of the n x p panel A on the GPU."""
     n = A.shape[0]
     a = ctp.device_panel(A, lda=lda)
-    opts = ctp.ctp_default_opts(method, u=u, small=small)
+    opts = ctp.ctp_default_opts(method, u=u, small=small, flags=flags)
     work = ctp.workspace(n, p, opts)
     f = ctp.ctp_supernode(a, opts, work=work)
     s = s_direct = None

@@ -117,3 +117,32 @@ def test_workspace_size_and_argument_checks(lib):
                                       ctypes.byref(o), 32, fake, 16, nul) == -16
     assert lib.ctp_ldlt_adjoint_batched(4, 100, 2, fake, 100, 10000, fake, fake, fake, fake, 100, 200, fake, 100,
                                         200, fake, 100, 9999, ctypes.byref(o), 32, fake, 1 << 40, nul) == -16
+
+
+def test_fused_and_batched_argument_checks(lib):
+    from paper_1305_2353_amd import ctp
+    o = ctp.ctp_default_opts("relaxed")
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(4096)
+    # fused Factor + Solve + Form: S leading dimension below n - p, workspace too small
+    assert lib.ctp_supernode(100, 10, fake, 100, ctypes.byref(o), fake, fake, fake, fake, fake, fake, 89,
+                             fake, 1 << 30, nul) == -12
+    assert lib.ctp_supernode(100, 10, fake, 100, ctypes.byref(o), fake, fake, fake, fake, fake, fake, 90,
+                             fake, 16, nul) == -13
+    # batched tasks: count, info, method and workspace checks
+    info = ctp.CtpBatchInfo()
+    info.count = 2
+    info.work_bytes = 1 << 20
+    tpp = ctp.ctp_default_opts("tpp")
+    args = (fake, ctypes.byref(info), fake)
+    assert lib.ctp_factor_supernode_batched(-1, *args, fake, fake, fake, fake, fake, ctypes.byref(o), fake,
+                                            1 << 20, nul) == -1
+    assert lib.ctp_factor_supernode_batched(3, *args, fake, fake, fake, fake, fake, ctypes.byref(o), fake,
+                                            1 << 20, nul) == -3
+    assert lib.ctp_factor_supernode_batched(2, *args, fake, fake, fake, fake, fake, ctypes.byref(tpp), fake,
+                                            1 << 20, nul) == -11
+    assert lib.ctp_solve_supernode_batched(2, *args, fake, fake, fake, fake, ctypes.byref(o), fake, 16,
+                                           nul) == -12
+    assert lib.ctp_schur_batched(2, *args, fake, fake, fake, nul, ctypes.byref(o), fake, 1 << 20, nul) == -5
+    assert lib.ctp_schur_batched(0, *args, fake, fake, fake, fake, ctypes.byref(o), fake, 1 << 20, nul) == -3
+
