@@ -22,7 +22,8 @@
  * Memory.  Every array argument is DEVICE memory owned by the caller (for
  *   example torch tensors).  The library never allocates, never
  *   synchronises the host and keeps no state between calls; scratch memory
- *   comes from the caller's workspace.  All work is enqueued on the given
+ *   comes from the caller's workspace (ctp_supernode_noalloc alone uses a
+ *   static device array of the library instead).  All work is enqueued on the given
  *   HIP stream; results (including nelim and status) are ready when that
  *   stream reaches them.  Integers stored on the device are int32.
  * Layout.  Matrices are column-major with a leading dimension; the panel
@@ -101,7 +102,11 @@ extern "C" {
 
 #define CTP_ERR_HIP_BASE (-1000)
 #define CTP_ERR_PANEL_TOO_WIDE (-900)  /* dense: delays grew a panel past CTP_MAX_P */
+#define CTP_ERR_SCRATCH_TOO_SMALL (-901) /* ctp_supernode_noalloc: the panel needs more
+                                            than CTP_NOALLOC_SCRATCH_BYTES of workspace */
 
+/* Device scratch of ctp_supernode_noalloc (bytes, per GPU). */
+#define CTP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 
 /* Largest p supported by the single-workgroup pivot search and the solve. */
 #define CTP_MAX_P 512
@@ -205,6 +210,22 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm,
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
                   int* perm, int* piv, double* d, int* nelim, int* status,
                   double* s, int lds, void* work, size_t lwork, hipStream_t stream);
+
+/* ctp_supernode for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same call without a workspace argument.  The workspace is a static
+ * device array of CTP_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library,
+ * one copy per GPU, held from the first call on that GPU until the process
+ * ends; the call allocates nothing.  Panels whose workspace
+ * (ctp_workspace_size) exceeds it are rejected with
+ * CTP_ERR_SCRATCH_TOO_SMALL, e.g. about n - p > 14000 at p = 512.  Every
+ * call on a GPU uses that GPU's one array, so calls that overlap on the
+ * same GPU (concurrent streams, threads) race; calls in one stream order
+ * are safe.  The stream must belong to the current device.  No step of the
+ * call relies on the array's contents from an earlier call. */
+int ctp_supernode_noalloc(int n, int p, double* a, int lda, const ctp_opts* opts,
+                          int* perm, int* piv, double* d, int* nelim, int* status,
+                          double* s, int lds, hipStream_t stream);
 
 /* Form task (Section 1): rows row0..row0+nrows-1 of the lower triangle of
  * S = L21 D11 L21^T, S of order n-p indexed like the rows of A21.  Entry

@@ -2,6 +2,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "common.h"
 
@@ -38,6 +39,34 @@ int launch_schur_batch(int count, const BatchNode* nodes, int method, long long 
                        int subtract, unsigned int* counter, int variant, int workgroups, hipStream_t stream);
 
 __global__ void clear_status_kernel(int* status) { *status = 0; }
+
+// Scratch of ctp_supernode_noalloc: one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// only stands for the symbol): the device address is looked up once per
+// device with hipGetSymbolAddress and kept in noalloc_ptr.
+static __device__ __align__(256) unsigned char scratch[CTP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void* noalloc_ptr[NOALLOC_MAX_DEVICES];
+static std::mutex noalloc_mu;
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device, with the device current).
+static int noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return CTP_ERR_HIP_BASE - (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return CTP_ERR_HIP_BASE - (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    noalloc_ptr[dev] = ptr;
+  }
+  *out = noalloc_ptr[dev];
+  return 0;
+}
 
 static bool valid_method(int m) { return m >= CTP_TPP && m <= CTP_RESTRICTED; }
 
@@ -173,6 +202,20 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* p
   Workspace ws = workspace_layout(n, p, opts->method);
   const double* w = reinterpret_cast<const double*>(static_cast<const unsigned char*>(work) + ws.w_off);
   return launch_schur_full(n, p, a, lda, w, ws.ldw, nelim, s, lds, tiled ? 1 : 0, 0, stream);
+}
+
+int ctp_supernode_noalloc(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                          double* d, int* nelim, int* status, double* s, int lds, hipStream_t stream) {
+  if (n < p) return -1;
+  if (p < 0) return -2;
+  if (check_opts(opts)) return -5;
+  const size_t need = workspace_layout(n, p, opts->method).total;
+  if (need > CTP_NOALLOC_SCRATCH_BYTES) return CTP_ERR_SCRATCH_TOO_SMALL;
+  void* work = nullptr;
+  int rc = noalloc_scratch(&work);
+  if (rc) return rc;
+  return ctp_supernode(n, p, a, lda, opts, perm, piv, d, nelim, status, s, lds, work, CTP_NOALLOC_SCRATCH_BYTES,
+                       stream);
 }
 
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,

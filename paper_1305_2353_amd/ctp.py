@@ -30,12 +30,14 @@ CTP_FLAG_S_TILED = 4
 SC_TILE = 128
 CTP_FLAG_S_SUBTRACT = 8
 CTP_ERR_PANEL_TOO_WIDE = -900
+CTP_ERR_SCRATCH_TOO_SMALL = -901
+CTP_NOALLOC_SCRATCH_BYTES = 64 << 20
 PREC_IDS = {"fp64": 0, "fp32": 1, "bf16": 2}
 CTP_MAX_P = 512
 
 # Every symbol declared in include/ctp.h.
 EXPORTED = ("ctp_default_opts", "ctp_version", "ctp_workspace_size", "ctp_compress",
-            "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode",
+            "ctp_factor_supernode", "ctp_solve_supernode", "ctp_supernode", "ctp_supernode_noalloc",
             "ctp_schur", "ctp_dense_workspace_size", "ctp_ldlt_dense", "ctp_ldlt_solve", "ctp_ldlt_refine",
             "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched", "ctp_factor_supernode_batched",
             "ctp_solve_supernode_batched", "ctp_schur_batched",
@@ -85,6 +87,7 @@ def load(path=LIB_PATH):
         "ctp_factor_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, SZ, P]),
         "ctp_solve_supernode": (I, [I, I, P, I, P, P, P, P, OPT, P, SZ, P]),
         "ctp_supernode": (I, [I, I, P, I, OPT, P, P, P, P, P, P, I, P, SZ, P]),
+        "ctp_supernode_noalloc": (I, [I, I, P, I, OPT, P, P, P, P, P, P, I, P]),
         "ctp_schur": (I, [I, I, P, I, P, P, P, I, I, P, I, OPT, P, SZ, P]),
         "ctp_dense_workspace_size": (I, [I, I, OPT, I, ctypes.POINTER(SZ)]),
         "ctp_ldlt_dense": (I, [I, I, P, I, OPT, P, P, P, P, ctypes.POINTER(I), P, SZ, P]),
@@ -248,6 +251,17 @@ def ctp_supernode(a, opts, work=None, outs=None, s=None):
     _check(load().ctp_supernode(n, p, _ptr(a), lda, ctypes.byref(opts), _ptr(perm), _ptr(piv), _ptr(d),
                                 _ptr(nelim), _ptr(status), sp, lds, _ptr(work), work.numel(), _stream()),
            "ctp_supernode")
+    return {"perm": perm[:p], "piv": piv[:p], "d": d[:2 * p], "nelim": nelim, "status": status}
+
+
+def ctp_supernode_noalloc(a, opts, outs=None, s=None):
+    """ctp_supernode with the library's static device scratch instead of a
+    caller workspace (no allocation inside the call)."""
+    n, p, lda = _panel_args(a)
+    perm, piv, d, nelim, status = outs if outs is not None else _outputs(p, a.device)
+    sp, lds = _s_args(s, n - p, opts)
+    _check(load().ctp_supernode_noalloc(n, p, _ptr(a), lda, ctypes.byref(opts), _ptr(perm), _ptr(piv), _ptr(d),
+                                        _ptr(nelim), _ptr(status), sp, lds, _stream()), "ctp_supernode_noalloc")
     return {"perm": perm[:p], "piv": piv[:p], "d": d[:2 * p], "nelim": nelim, "status": status}
 
 

@@ -146,3 +146,16 @@ def test_fused_and_batched_argument_checks(lib):
     assert lib.ctp_schur_batched(2, *args, fake, fake, fake, nul, ctypes.byref(o), fake, 1 << 20, nul) == -5
     assert lib.ctp_schur_batched(0, *args, fake, fake, fake, fake, ctypes.byref(o), fake, 1 << 20, nul) == -3
 
+
+def test_noalloc_rejects_panels_beyond_its_scratch(lib):
+    # checked on the host before the device is touched
+    from paper_1305_2353_amd import ctp
+    o = ctp.ctp_default_opts("relaxed")
+    fake = ctypes.c_void_p(4096)
+    sz = ctypes.c_size_t()
+    assert lib.ctp_workspace_size(20000, 512, ctypes.byref(o), ctypes.byref(sz)) == 0
+    assert sz.value > ctp.CTP_NOALLOC_SCRATCH_BYTES
+    assert lib.ctp_supernode_noalloc(20000, 512, fake, 20000, ctypes.byref(o), fake, fake, fake, fake, fake,
+                                     None, 1, None) == ctp.CTP_ERR_SCRATCH_TOO_SMALL
+    assert lib.ctp_supernode_noalloc(5, 10, fake, 5, ctypes.byref(o), fake, fake, fake, fake, fake, None, 1,
+                                     None) == -1
