@@ -13,8 +13,8 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
 int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, int abs_update,
                         int root, int one_wg, double u, double small, int* perm, int* piv, double* d,
                         int* nelim, int* status, void* state, double* wbuf, hipStream_t stream);
-int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                 const double* d, const int* nelim, double* w, int ldw, double* lc, hipStream_t stream);
+int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv, const double* d,
+                 const int* nelim, double* w, int ldw, double* lc, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream);

@@ -56,7 +56,7 @@ struct Workspace {
   size_t wb_off = 0;      // pivot-search batch of pivot-column values
   size_t w_off = 0;       // compressed / restricted: (n-p) x p doubles, solve gather buffer
   int ldw = 1;
-  size_t lc_off = 0;      // solve: compact copy of A11 after the pivot search (p x p, ld p)
+  size_t lc_off = 0;      // solve: L (masked, unit diagonal) after the pivot search (p x p, ld p)
   size_t misc_off = 0;    // 64 ints of counters / flags
   size_t total = 0;
   int relaxed_chunks = 0;

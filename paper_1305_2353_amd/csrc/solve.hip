@@ -4,52 +4,17 @@
 //     W_E  = x_E (L_EE^T)^-1          (forward substitution, L unit lower)
 //     x_d' = x_d - W_E L_dE^T         (delayed columns)
 //     L21  = W_E D^-1                 (1x1 and 2x2 blocks)
-//
-// Two kernels:
-//  1. gather: W = A21 P^T column by column into the workspace (the
-//     permutation is applied once, as a copy; the panel can then be
-//     overwritten in place without losing original columns);
-//  2. blocked left-looking triangular solve on the matrix cores.  One wave
-//     owns 16 rows and walks the p columns in blocks of 16:
-//        X_b = W_b - W_{<b} L_{b,<b}^T        (v_mfma_f64_16x16x4, K = 16b)
-//        forward substitution inside the 16 x 16 diagonal block of L
-//        (pivot values broadcast across the lanes that hold a row);
-//     the solved block goes back to the workspace (the A operand of later
-//     blocks) and, multiplied by D^-1, to the panel as L21.  A 2x2 pivot
-//     that straddles two blocks is finished when the second block is done.
-//  Delayed columns (positions >= nelim) receive the GEMM and in-block
-//  updates from every eliminated column and are written unscaled.
+// W = L21 D stays in the workspace as the Form's second operand.  The
+// kernels are described with solve_rl_body below; after threshold partial
+// pivoting (which leaves L21 in the panel) form_w_kernel only writes W.
+
+#include <type_traits>
 
 #include "common.h"
 
 namespace ctp {
 
 typedef double d4s __attribute__((ext_vector_type(4)));
-
-constexpr int SOLVE_THREADS = 256;   // 4 waves, 16 rows each
-constexpr int SOLVE_ROWS = 64;
-
-// Column j of W = A21 P^T (rows chunk*4096 ..), and with the first chunk
-// column j of A11 into the compact p x p copy lc: the solve's L operand,
-// whose columns are then 8p bytes apart instead of 8 lda bytes (every step
-// of the solve reads four columns of L; at lda = 100000 those sit in four
-// different pages).
-CTP_DEV void solve_gather_body(int r, int p, const double* __restrict__ a, int lda, const int* __restrict__ perm,
-                               double* __restrict__ w, int ldw, double* __restrict__ lc, int j, int chunk) {
-  const double* src = a + p + (size_t)perm[j] * lda;
-  double* dst = w + (size_t)j * ldw;
-  const int i0 = chunk * 4096;
-  const int i1 = min(r, i0 + 4096);
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
-  if (chunk == 0)
-    for (int i = threadIdx.x; i < p; i += blockDim.x) lc[(size_t)j * p + i] = a[(size_t)j * lda + i];
-}
-
-__global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a, int lda,
-                                                         const int* __restrict__ perm, double* __restrict__ w,
-                                                         int ldw, double* __restrict__ lc) {
-  solve_gather_body(r, p, a, lda, perm, w, ldw, lc, blockIdx.y, blockIdx.x);
-}
 
 // 2x2 pivot inverse entries, scaled as in the pivot search.
 CTP_DEV void inv2x2(double a11, double a21, double a22, double& i11, double& i21, double& i22) {
@@ -59,220 +24,6 @@ CTP_DEV void inv2x2(double a11, double a21, double a22, double& i11, double& i21
   i11 = f * a22;
   i21 = -(f * a21);
   i22 = f * a11;
-}
-
-__shared__ int slv_piv[CTP_MAX_P + 32];
-__shared__ double slv_d[2 * CTP_MAX_P + 64];
-
-CTP_DEV void solve_mfma_body(int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
-                             const double* __restrict__ d, const int* __restrict__ nelim_p,
-                             double* __restrict__ w, int ldw, const double* __restrict__ lc, int bx) {
-  int* piv_s = slv_piv;
-  double* d_s = slv_d;
-  for (int k = threadIdx.x; k < p + 32; k += SOLVE_THREADS) {
-    piv_s[k] = k < p ? piv[k] : PIV_DELAYED;
-    d_s[2 * k] = k < p ? d[2 * k] : 0.0;
-    d_s[2 * k + 1] = k < p ? d[2 * k + 1] : 0.0;
-  }
-  __syncthreads();
-
-  const int nelim = min(max(*nelim_p, 0), p);
-  const int lane = threadIdx.x & 63;
-  const int r0 = (bx * SOLVE_THREADS + (int)threadIdx.x) / 64 * 16;   // first row of this wave
-  if (r0 >= r) return;
-  double* a21 = a + p;
-  const int ga = lane >> 4;          // accumulator rows ga + 4q
-  const int c = lane & 15;           // accumulator column
-  const int fr = lane & 15;          // fragment row (A operand) / column (B operand)
-  const int fk = lane >> 4;          // fragment k
-  const int rmax = r - 1;
-  const int arow = min(r0 + fr, rmax);
-  int rows[4];
-  bool rv[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    rows[q] = r0 + ga + 4 * q;
-    rv[q] = rows[q] < r;
-    rows[q] = min(rows[q], rmax);
-  }
-
-  const int nb = (p + 15) / 16;
-  double carry[4] = {0.0, 0.0, 0.0, 0.0};   // previous block's column 15 (lanes c == 15)
-  for (int b = 0; b < nb; ++b) {
-    const int j0 = 16 * b;
-    const int jc = j0 + c;                   // this lane's column
-    const bool cv = jc < p;
-    const int jcc = min(jc, p - 1);
-    d4s acc;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = w[(size_t)jcc * ldw + rows[q]];
-
-    // X_b -= W_{<b} L_{b,<b}^T over the eliminated columns k < min(j0, nelim):
-    // 16 columns of k per step on four independent accumulators (the MFMAs
-    // of a step do not wait for each other), the next step's fragments
-    // loaded while the current step's products run.  Every step but the
-    // last is full and cannot meet the 2x2 pivot that may straddle the
-    // block boundary (k = j0 - 1), so it runs on pointer increments without
-    // masks; the last step takes the masked loads.
-    const int kend = min(j0, nelim);
-    const int bj = min(j0 + fr, p - 1);      // B operand: row j0+fr of L
-    const bool brow = j0 + fr < p;
-    if (kend > 0) {
-      const int klast = (kend - 1) / 16 * 16;   // first k of the last step
-      d4s part[4];
-      part[0] = acc;
-#pragma unroll
-      for (int u = 1; u < 4; ++u) part[u] = d4s{0.0, 0.0, 0.0, 0.0};
-      const size_t wstep = (size_t)4 * ldw, lstep = (size_t)4 * p;
-      const double* wp = w + (size_t)fk * ldw + arow;   // W(arow, k), k = fk + 4u + k0
-      const double* lp = lc + (size_t)fk * p + bj;      // L(bj, k)
-      double an[4], bn[4];
-      if (klast > 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          an[u] = -wp[u * wstep];
-          bn[u] = brow ? lp[u * lstep] : 0.0;
-        }
-      }
-      for (int k0 = 0; k0 < klast; k0 += 16) {
-        double ac[4], bc[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          ac[u] = an[u];
-          bc[u] = bn[u];
-        }
-        wp += 4 * wstep;
-        lp += 4 * lstep;
-        if (k0 + 16 < klast) {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            an[u] = -wp[u * wstep];
-            bn[u] = brow ? lp[u * lstep] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ac[u], bc[u], part[u], 0, 0, 0);
-      }
-      // last step: k = klast .. kend-1
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = klast + 4 * u + fk;
-        const bool kv = k < kend;
-        const int kc = kv ? k : 0;
-        double af = w[(size_t)kc * ldw + arow];
-        double bf = CM(lc, bj, kc, p);
-        // L(j0, j0-1) is the in-block entry of a 2x2 pivot straddling the
-        // block boundary: it holds D, not L.
-        const bool straddle = (j0 + fr == k + 1) && piv_s[kc] == PIV_2X2_FIRST;
-        af = kv ? -af : 0.0;
-        bf = (kv && !straddle && brow) ? bf : 0.0;
-        part[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, part[u], 0, 0, 0);
-      }
-      acc = (part[0] + part[1]) + (part[2] + part[3]);
-    }
-
-    // forward substitution inside the block
-    const int kkend = min(16, nelim - j0);
-    for (int kk = 0; kk < kkend; ++kk) {
-      const int k = j0 + kk;
-      double lv = CM(lc, jcc, k, p);
-      const bool keep = cv && c > kk && !(c == kk + 1 && piv_s[k] == PIV_2X2_FIRST);
-      lv = keep ? lv : 0.0;
-      if (piv_s[k] == PIV_ZERO && c == kk) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = 0.0;
-      }
-      const int src = (lane & 48) | kk;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double xk = __shfl(acc[q], src, 64);
-        acc[q] = fma(-xk, lv, acc[q]);
-      }
-    }
-
-    // solved block -> workspace (A operand of later blocks)
-    if (cv && jc < nelim) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (rv[q]) w[(size_t)jc * ldw + rows[q]] = acc[q];
-    }
-    __threadfence_block();
-
-    // outputs: L21 = W D^-1 for eliminated columns, raw for delayed ones
-    const int pt = piv_s[jcc];
-    double nxt[4], prv[4], prevc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      nxt[q] = __shfl(acc[q], (lane + 1) & 63, 64);
-      prv[q] = __shfl(acc[q], (lane + 63) & 63, 64);
-      prevc[q] = __shfl(carry[q], (lane & 48) | 15, 64);
-    }
-    if (cv) {
-      double i11 = 0.0, i21 = 0.0, i22 = 0.0;
-      if (jc < nelim && (pt == PIV_2X2_FIRST || pt == PIV_2X2_SECOND)) {
-        const int k = pt == PIV_2X2_FIRST ? jc : jc - 1;
-        inv2x2(d_s[2 * k], d_s[2 * k + 1], d_s[2 * k + 2], i11, i21, i22);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!rv[q]) continue;
-        double* rowp = a21 + rows[q];
-        if (jc >= nelim) {
-          rowp[(size_t)jc * lda] = acc[q];
-        } else if (pt == PIV_1X1) {
-          rowp[(size_t)jc * lda] = acc[q] / d_s[2 * jc];
-        } else if (pt == PIV_ZERO) {
-          rowp[(size_t)jc * lda] = 0.0;
-        } else if (pt == PIV_2X2_FIRST) {
-          if (c < 15) rowp[(size_t)jc * lda] = acc[q] * i11 + nxt[q] * i21;
-          // c == 15: finished with the next block
-        } else {
-          const double w1 = c > 0 ? prv[q] : prevc[q];
-          const double w2 = acc[q];
-          rowp[(size_t)jc * lda] = w1 * i21 + w2 * i22;
-          if (c == 0) rowp[(size_t)(jc - 1) * lda] = w1 * i11 + w2 * i21;
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) carry[q] = acc[q];
-  }
-}
-
-__global__ __launch_bounds__(SOLVE_THREADS, 3) void solve_mfma_kernel(
-    int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
-    const double* __restrict__ d, const int* __restrict__ nelim_p, double* __restrict__ w, int ldw,
-    const double* __restrict__ lc) {
-  solve_mfma_body(r, p, a, lda, piv, d, nelim_p, w, ldw, lc, blockIdx.x);
-}
-
-// Batched: the node is blockIdx.z (gather) / blockIdx.y (solve).
-__global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
-  const BatchNode& nd = nodes[blockIdx.z];
-  const int r = nd.n - nd.p;
-  if ((int)blockIdx.y >= nd.p || (int)blockIdx.x * 4096 >= r) return;
-  const Workspace ws = workspace_layout(nd.n, nd.p, method);
-  solve_gather_body(r, nd.p, nd.a, nd.lda, nd.perm, reinterpret_cast<double*>(nd.work + ws.w_off), ws.ldw,
-                    reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y, blockIdx.x);
-}
-
-__global__ __launch_bounds__(SOLVE_THREADS, 3) void solve_mfma_batch_kernel(const BatchNode* __restrict__ nodes,
-                                                                         int method) {
-  const BatchNode& nd = nodes[blockIdx.y];
-  const int r = nd.n - nd.p;
-  if ((int)blockIdx.x * SOLVE_ROWS >= r) return;
-  const Workspace ws = workspace_layout(nd.n, nd.p, method);
-  solve_mfma_body(r, nd.p, nd.a, nd.lda, nd.piv, nd.d, nd.nelim, reinterpret_cast<double*>(nd.work + ws.w_off),
-                  ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), blockIdx.x);
-}
-
-int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream) {
-  if (count <= 0 || max_r <= 0 || max_p <= 0) return 0;
-  solve_gather_batch_kernel<<<dim3((max_r + 4095) / 4096, max_p, count), 256, 0, stream>>>(nodes, method);
-  solve_mfma_batch_kernel<<<dim3((max_r + SOLVE_ROWS - 1) / SOLVE_ROWS, count), SOLVE_THREADS, 0, stream>>>(nodes,
-                                                                                                        method);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
 
 // W = L21 D for the eliminated columns, from L21 and D (used after the
@@ -315,14 +66,312 @@ int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const 
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
 
-int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv,
-                 const double* d, const int* nelim, double* w, int ldw, double* lc, hipStream_t stream) {
+// ---------------------------------------------------------------------------
+// Blocked triangular solve: W = X L'^-T, X = A21 P^T, with L' the unit lower
+// triangular p x p matrix of the factorization modified so that
+//   * the entry below the first column of a 2x2 pivot (it holds D) is 0,
+//   * the column of a zero pivot is 0 below the diagonal (its W is dropped),
+//   * a delayed column (position >= nelim) is a unit column; its row keeps
+//     the L_dE entries,
+// so that the rows of the result are [ W_E , X_d - W_E L_dE^T ]: W of the
+// eliminated columns and the updated delayed columns at once.  The columns
+// go in panels of up to 256:
+//   gather   X into the workspace, L' (masked as above) into a compact
+//            p x p copy lc;
+//   diag     per panel: each wave takes 16 rows and solves them against the
+//            panel's diagonal block of L', right-looking in 16-column
+//            blocks held as FP64 matrix-core accumulators: forward
+//            substitution inside the 16 x 16 diagonal block (column kk
+//            broadcast to the lanes of its rows by a DPP row share), then
+//            the product with the block's W subtracted from the later
+//            blocks of the panel on the matrix cores.  No barriers: the
+//            waves of a workgroup are independent and many per CU hide the
+//            latency of the chain;
+//   update   between panels: X_2 -= W_1 L'_21^T, the Form's MFMA tile
+//            routine with a subtracting epilogue (schur.hip);
+//   scale    L21 = W D^-1 into the panel (delayed columns copied
+//            unscaled), W kept in the workspace for the Form.
+// Every step is exact substitution or an exact product: the accuracy is
+// that of a blocked forward substitution.
+// ---------------------------------------------------------------------------
+
+constexpr int SV_PANEL = 256;             // columns per panel
+constexpr int SV_LDW = 17;                // LDS stride of a 16-entry column (padded)
+
+// X column j (rows chunk*4096..) = A21 column perm[j]; with the first chunk,
+// column j of L' (rows 0..p-1) into lc.
+CTP_DEV void solve_gather_body(int r, int p, const double* __restrict__ a, int lda, const int* __restrict__ perm,
+                               const int* __restrict__ piv, const int* __restrict__ nelim_p, double* __restrict__ x,
+                               int ldx, double* __restrict__ lc, int j, int chunk) {
+  const double* src = a + p + (size_t)perm[j] * lda;
+  double* dst = x + (size_t)j * ldx;
+  const int i0 = chunk * 4096;
+  const int i1 = min(r, i0 + 4096);
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
+  if (chunk == 0) {
+    const int nelim = min(max(*nelim_p, 0), p);
+    const int pj = piv[j];
+    const bool col = j < nelim && pj != PIV_ZERO;
+    for (int i = threadIdx.x; i < p; i += blockDim.x) {
+      const bool keep = col && i > j && !(i == j + 1 && pj == PIV_2X2_FIRST);
+      lc[(size_t)j * p + i] = keep ? a[(size_t)j * lda + i] : (i == j ? 1.0 : 0.0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a, int lda,
+                                                         const int* __restrict__ perm, const int* __restrict__ piv,
+                                                         const int* __restrict__ nelim_p, double* __restrict__ x,
+                                                         int ldx, double* __restrict__ lc) {
+  solve_gather_body(r, p, a, lda, perm, piv, nelim_p, x, ldx, lc, blockIdx.y, blockIdx.x);
+}
+
+// DPP move of a double: every lane <- lane k of its row of 16.
+constexpr int SV_ROW_SHARE = 0x150;
+
+template <int K>
+CTP_DEV double sv_share(double x) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(bits & 0xffffffffull), SV_ROW_SHARE + K, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(bits >> 32), SV_ROW_SHARE + K, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// One wave: rows r0..r0+15 of the panel of columns c0..c0+16 NBP-1 of x
+// (in place).  Accumulator layout: element q of lane l of block b is row
+// l/16 + 4q, column c0 + 16 b + l % 16.
+template <int NBP>
+CTP_DEV void solve_diag_wave(int r, int p, int c0, const int* __restrict__ piv, int nelim, double* __restrict__ x,
+                             int ldx, const double* __restrict__ lc, double* stage, int r0) {
+  const int lane = threadIdx.x & 63;
+  const int ga = lane >> 4, c = lane & 15;
+  const int nbe = min(NBP, (nelim - c0 + 15) / 16);   // blocks of the panel with eliminated columns
+  if (nbe <= 0) return;                                // a panel of delayed columns: X is final
+  int rows[4];
+  bool rv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = r0 + ga + 4 * q;
+    rv[q] = i < r;
+    rows[q] = min(i, r - 1);
+  }
+  d4s acc[NBP];
+#pragma unroll
+  for (int b = 0; b < NBP; ++b) {
+    const int j = min(c0 + 16 * b + c, p - 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[b][q] = x[(size_t)j * ldx + rows[q]];
+  }
+  for (int b = 0; b < nbe; ++b) {
+    const int j0 = c0 + 16 * b;
+    const int jc = min(j0 + c, p - 1);
+    const int kkend = min(16, nelim - j0);
+    // the diagonal block's L' column entries of this lane's column
+    double lrow[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) lrow[kk] = lc[(size_t)min(j0 + kk, p - 1) * p + jc];
+    const unsigned zmask = (unsigned)__ballot(j0 + c < p && piv[jc] == PIV_ZERO) & 0xffffu;
+    d4s xb = acc[0];
+#pragma unroll
+    for (int cb = 1; cb < NBP; ++cb) xb = cb == b ? acc[cb] : xb;
+    double xv[4] = {xb[0], xb[1], xb[2], xb[3]};
+    auto step = [&](auto kkc) __attribute__((always_inline)) {
+      constexpr int kk = decltype(kkc)::value;
+      if (kk >= kkend) return;
+      if (((zmask >> kk) & 1u) && c == kk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = 0.0;
+      }
+      const double lv = c > kk ? lrow[kk] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[q] = fma(-sv_share<kk>(xv[q]), lv, xv[q]);
+    };
+    step(std::integral_constant<int, 0>{});
+    step(std::integral_constant<int, 1>{});
+    step(std::integral_constant<int, 2>{});
+    step(std::integral_constant<int, 3>{});
+    step(std::integral_constant<int, 4>{});
+    step(std::integral_constant<int, 5>{});
+    step(std::integral_constant<int, 6>{});
+    step(std::integral_constant<int, 7>{});
+    step(std::integral_constant<int, 8>{});
+    step(std::integral_constant<int, 9>{});
+    step(std::integral_constant<int, 10>{});
+    step(std::integral_constant<int, 11>{});
+    step(std::integral_constant<int, 12>{});
+    step(std::integral_constant<int, 13>{});
+    step(std::integral_constant<int, 14>{});
+    step(std::integral_constant<int, 15>{});
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xb[q] = xv[q];
+#pragma unroll
+    for (int cb = 0; cb < NBP; ++cb) acc[cb] = cb == b ? xb : acc[cb];
+    if (b + 1 >= NBP) break;
+    // W of the block's eliminated columns as A fragments (row l % 16,
+    // column l/16 + 4u), through the wave's staging area
+    const bool elim = j0 + c < nelim;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) stage[c * SV_LDW + ga + 4 * q] = elim ? xv[q] : 0.0;
+    double af[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) af[u] = -stage[(4 * u + ga) * SV_LDW + c];
+    // later blocks of the panel: B fragment L'(16 cb' + l % 16, j0 + 4u + l/16)
+#pragma unroll
+    for (int cb = 1; cb < NBP; ++cb) {
+      if (cb <= b) continue;
+      const int jr = min(c0 + 16 * cb + c, p - 1);
+      double bf[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bf[u] = lc[(size_t)min(j0 + 4 * u + ga, p - 1) * p + jr];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u], acc[cb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < NBP; ++b) {
+    const int j = c0 + 16 * b + c;
+    if (j >= p) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (rv[q]) x[(size_t)j * ldx + rows[q]] = acc[b][q];
+  }
+}
+
+template <int NBP>
+__global__ __launch_bounds__(256, 2) void solve_diag_kernel(int r, int p, int c0, const int* __restrict__ piv,
+                                                       const int* __restrict__ nelim_p, double* __restrict__ x,
+                                                       int ldx, const double* __restrict__ lc) {
+  __shared__ double stage[4][16 * SV_LDW];
+  const int wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.x * 4 + wave) * 16;
+  if (r0 >= r) return;
+  solve_diag_wave<NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, stage[wave], r0);
+}
+
+// Rows chunk*4096.. of column k: the workspace holds W (eliminated) or the
+// final delayed column; the panel gets L21 = W D^-1 or the delayed column.
+// The thread of the first column of a 2x2 pivot writes both columns.
+CTP_DEV void solve_scale_body(int r, int p, double* __restrict__ a, int lda, const int* __restrict__ piv,
+                              const double* __restrict__ d, const int* __restrict__ nelim_p,
+                              const double* __restrict__ w, int ldw, int k, int chunk) {
+  const int nelim = min(max(*nelim_p, 0), p);
+  const int pk = piv[k];
+  if (k < nelim && pk == PIV_2X2_SECOND) return;
+  double* a21 = a + p;
+  const int i0 = chunk * 4096;
+  const int i1 = min(r, i0 + 4096);
+  const double* wk = w + (size_t)k * ldw;
+  double* ak = a21 + (size_t)k * lda;
+  if (k >= nelim) {
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) ak[i] = wk[i];
+  } else if (pk == PIV_1X1) {
+    const double rd = 1.0 / d[2 * k];
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) ak[i] = wk[i] * rd;
+  } else if (pk == PIV_ZERO) {
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) ak[i] = 0.0;
+  } else {
+    double i11, i21, i22;
+    inv2x2(d[2 * k], d[2 * k + 1], d[2 * k + 2], i11, i21, i22);
+    double* ak1 = ak + lda;
+    const double* wk1 = wk + ldw;
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+      const double w1 = wk[i], w2 = wk1[i];
+      ak[i] = w1 * i11 + w2 * i21;
+      ak1[i] = w1 * i21 + w2 * i22;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void solve_scale_kernel(int r, int p, double* __restrict__ a, int lda,
+                                                        const int* __restrict__ piv, const double* __restrict__ d,
+                                                        const int* __restrict__ nelim_p, const double* __restrict__ w,
+                                                        int ldw) {
+  solve_scale_body(r, p, a, lda, piv, d, nelim_p, w, ldw, blockIdx.y, blockIdx.x);
+}
+
+// Batched: the node is blockIdx.z (gather, scale) or blockIdx.y (diag).
+__global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
+  const BatchNode& nd = nodes[blockIdx.z];
+  const int r = nd.n - nd.p;
+  if ((int)blockIdx.y >= nd.p || (int)blockIdx.x * 4096 >= r) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, method);
+  solve_gather_body(r, nd.p, nd.a, nd.lda, nd.perm, nd.piv, nd.nelim, reinterpret_cast<double*>(nd.work + ws.w_off),
+                    ws.ldw, reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y, blockIdx.x);
+}
+
+template <int NBP>
+__global__ __launch_bounds__(256, 2) void solve_diag_batch_kernel(const BatchNode* __restrict__ nodes, int method, int c0) {
+  __shared__ double stage[4][16 * SV_LDW];
+  const BatchNode& nd = nodes[blockIdx.y];
+  const int r = nd.n - nd.p;
+  const int wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.x * 4 + wave) * 16;
+  if (r0 >= r || c0 >= nd.p) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, method);
+  solve_diag_wave<NBP>(r, nd.p, c0, nd.piv, min(max(*nd.nelim, 0), nd.p), reinterpret_cast<double*>(nd.work + ws.w_off),
+                       ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), stage[wave], r0);
+}
+
+__global__ __launch_bounds__(256) void solve_scale_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
+  const BatchNode& nd = nodes[blockIdx.z];
+  const int r = nd.n - nd.p;
+  if ((int)blockIdx.y >= nd.p || (int)blockIdx.x * 4096 >= r) return;
+  const Workspace ws = workspace_layout(nd.n, nd.p, method);
+  solve_scale_body(r, nd.p, nd.a, nd.lda, nd.piv, nd.d, nd.nelim, reinterpret_cast<const double*>(nd.work + ws.w_off),
+                   ws.ldw, blockIdx.y, blockIdx.x);
+}
+
+int launch_solve_update(int r, int p, int c0, double* x, int ldx, const double* lc, hipStream_t stream);
+int launch_solve_update_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int c0,
+                              hipStream_t stream);
+
+template <typename F>
+static void solve_diag_dispatch(int nbp, F&& f) {
+  if (nbp <= 4) f(std::integral_constant<int, 4>{});
+  else if (nbp <= 8) f(std::integral_constant<int, 8>{});
+  else f(std::integral_constant<int, 16>{});
+}
+
+int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv, const double* d,
+                 const int* nelim, double* w, int ldw, double* lc, hipStream_t stream) {
   const int r = n - p;
   if (r <= 0 || p <= 0) return 0;
-  dim3 gg((r + 4095) / 4096, p);
-  solve_gather_kernel<<<gg, 256, 0, stream>>>(r, p, a, lda, perm, w, ldw, lc);
-  solve_mfma_kernel<<<(r + SOLVE_ROWS - 1) / SOLVE_ROWS, SOLVE_THREADS, 0, stream>>>(r, p, a, lda, piv, d,
-                                                                                 nelim, w, ldw, lc);
+  const dim3 cols((r + 4095) / 4096, p);
+  solve_gather_kernel<<<cols, 256, 0, stream>>>(r, p, a, lda, perm, piv, nelim, w, ldw, lc);
+  const unsigned grid = (unsigned)((r + 63) / 64);
+  for (int c0 = 0; c0 < p; c0 += SV_PANEL) {
+    if (c0 > 0) {
+      int rc = launch_solve_update(r, p, c0, w, ldw, lc, stream);
+      if (rc) return rc;
+    }
+    const int nbp = (min(SV_PANEL, p - c0) + 15) / 16;
+    solve_diag_dispatch(nbp, [&](auto k) {
+      constexpr int NBP = decltype(k)::value;
+      solve_diag_kernel<NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
+    });
+  }
+  solve_scale_kernel<<<cols, 256, 0, stream>>>(r, p, a, lda, piv, d, nelim, w, ldw);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream) {
+  if (count <= 0 || max_r <= 0 || max_p <= 0) return 0;
+  const dim3 cols((max_r + 4095) / 4096, max_p, count);
+  solve_gather_batch_kernel<<<cols, 256, 0, stream>>>(nodes, method);
+  const dim3 grid((max_r + 63) / 64, count);
+  for (int c0 = 0; c0 < max_p; c0 += SV_PANEL) {
+    if (c0 > 0) {
+      int rc = launch_solve_update_batch(count, nodes, method, max_p, max_r, c0, stream);
+      if (rc) return rc;
+    }
+    const int nbp = (min(SV_PANEL, max_p - c0) + 15) / 16;
+    solve_diag_dispatch(nbp, [&](auto k) {
+      constexpr int NBP = decltype(k)::value;
+      solve_diag_batch_kernel<NBP><<<grid, 256, 0, stream>>>(nodes, method, c0);
+    });
+  }
+  solve_scale_batch_kernel<<<cols, 256, 0, stream>>>(nodes, method);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
