@@ -137,115 +137,181 @@ CTP_DEV double sv_share(double x) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// One wave: rows r0..r0+15 of the panel of columns c0..c0+16 NBP-1 of x
-// (in place).  Accumulator layout: element q of lane l of block b is row
-// l/16 + 4q, column c0 + 16 b + l % 16.
+// LDS of the diagonal-panel kernel: the 16 columns of L' of the current
+// block (rows from the block's first column to the end of the panel), two
+// buffers, and a transposition area per wave.  Entry (row j0 + i, column j0
+// + kk) of block b's buffer is at lbuf[kk * SV_LROWS + i]; the stride (16
+// mod 32 doubles) puts the four 16-lane groups of a wave, which read four
+// consecutive columns, on distinct banks.
+constexpr int SV_LROWS = SV_PANEL + 16;
+constexpr int SV_LBUF = 16 * SV_LROWS;
+
+// LDS-only workgroup barrier: outstanding global loads and stores are not
+// waited for (the compiler waits for each load where its value is used).
+CTP_DEV void sv_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// One workgroup of four waves, 16 rows each: rows r0.. of the panel of
+// columns c0..c0+16 NBP-1 of x (in place).  Accumulator layout: element q of
+// lane l is row l/16 + 4q, column l % 16 of its block.
+//
+// acc[k] holds block b + k while block b is worked: the accumulators of the
+// blocks to come collect the updates of earlier blocks, and a block's X is
+// added one iteration ahead (loaded at the start of the iteration, added at
+// its end, when the array has moved down by one).  Each iteration loads one
+// block of X and stores one, and the L' columns of the next block travel
+// through registers (fetched at the start of an iteration, written to LDS
+// at its end): the memory traffic is spread over the whole loop and hidden
+// behind the arithmetic of the current block.
 template <int NBP>
-CTP_DEV void solve_diag_wave(int r, int p, int c0, const int* __restrict__ piv, int nelim, double* __restrict__ x,
-                             int ldx, const double* __restrict__ lc, double* stage, int r0) {
-  const int lane = threadIdx.x & 63;
+CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, int nelim, double* __restrict__ x,
+                           int ldx, const double* __restrict__ lc, double* lsh, double* stage, int r0) {
+  const int tid = threadIdx.x, lane = tid & 63;
   const int ga = lane >> 4, c = lane & 15;
   const int nbe = min(NBP, (nelim - c0 + 15) / 16);   // blocks of the panel with eliminated columns
   if (nbe <= 0) return;                                // a panel of delayed columns: X is final
+  const int nb = min(NBP, (p - c0 + 15) / 16);         // blocks with columns below p
   int rows[4];
-  bool rv[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = r0 + ga + 4 * q;
-    rv[q] = i < r;
-    rows[q] = min(i, r - 1);
-  }
-  d4s acc[NBP];
+  for (int q = 0; q < 4; ++q) rows[q] = min(r0 + ga + 4 * q, r - 1);
+  // bit b: column c0 + 16 b + c has a zero pivot
+  int pv[NBP];
 #pragma unroll
-  for (int b = 0; b < NBP; ++b) {
+  for (int b = 0; b < NBP; ++b) pv[b] = piv[min(c0 + 16 * b + c, p - 1)];
+  unsigned zb = 0;
+#pragma unroll
+  for (int b = 0; b < NBP; ++b) zb |= (c0 + 16 * b + c < p && pv[b] == PIV_ZERO ? 1u : 0u) << b;
+  // L' staging: thread t carries column j0 + t/16, rows j0 + t%16 + 16 m
+  const int skk = tid >> 4, si = tid & 15;
+  double lreg[NBP];
+  auto fetch_l = [&](int b) __attribute__((always_inline)) {
+    const int j0 = c0 + 16 * b;
+    const int col = j0 + skk;
+#pragma unroll
+    for (int m = 0; m < NBP; ++m) {
+      const int row = j0 + si + 16 * m;
+      if (m < NBP - b) lreg[m] = row < p && col < p ? lc[(size_t)col * p + row] : 0.0;
+    }
+  };
+  auto put_l = [&](int b) __attribute__((always_inline)) {
+    double* buf = lsh + (b & 1) * SV_LBUF + skk * SV_LROWS + si;
+#pragma unroll
+    for (int m = 0; m < NBP; ++m)
+      if (m < NBP - b) buf[16 * m] = lreg[m];
+  };
+  auto load_x = [&](int b, double* v) __attribute__((always_inline)) {
     const int j = min(c0 + 16 * b + c, p - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[b][q] = x[(size_t)j * ldx + rows[q]];
-  }
-  for (int b = 0; b < nbe; ++b) {
-    const int j0 = c0 + 16 * b;
-    const int jc = min(j0 + c, p - 1);
-    const int kkend = min(16, nelim - j0);
-    // the diagonal block's L' column entries of this lane's column
-    double lrow[16];
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) lrow[kk] = lc[(size_t)min(j0 + kk, p - 1) * p + jc];
-    const unsigned zmask = (unsigned)__ballot(j0 + c < p && piv[jc] == PIV_ZERO) & 0xffffu;
-    d4s xb = acc[0];
-#pragma unroll
-    for (int cb = 1; cb < NBP; ++cb) xb = cb == b ? acc[cb] : xb;
-    double xv[4] = {xb[0], xb[1], xb[2], xb[3]};
-    auto step = [&](auto kkc) __attribute__((always_inline)) {
-      constexpr int kk = decltype(kkc)::value;
-      if (kk >= kkend) return;
-      if (((zmask >> kk) & 1u) && c == kk) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) xv[q] = 0.0;
-      }
-      const double lv = c > kk ? lrow[kk] : 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) xv[q] = fma(-sv_share<kk>(xv[q]), lv, xv[q]);
-    };
-    step(std::integral_constant<int, 0>{});
-    step(std::integral_constant<int, 1>{});
-    step(std::integral_constant<int, 2>{});
-    step(std::integral_constant<int, 3>{});
-    step(std::integral_constant<int, 4>{});
-    step(std::integral_constant<int, 5>{});
-    step(std::integral_constant<int, 6>{});
-    step(std::integral_constant<int, 7>{});
-    step(std::integral_constant<int, 8>{});
-    step(std::integral_constant<int, 9>{});
-    step(std::integral_constant<int, 10>{});
-    step(std::integral_constant<int, 11>{});
-    step(std::integral_constant<int, 12>{});
-    step(std::integral_constant<int, 13>{});
-    step(std::integral_constant<int, 14>{});
-    step(std::integral_constant<int, 15>{});
-#pragma unroll
-    for (int q = 0; q < 4; ++q) xb[q] = xv[q];
-#pragma unroll
-    for (int cb = 0; cb < NBP; ++cb) acc[cb] = cb == b ? xb : acc[cb];
-    if (b + 1 >= NBP) break;
-    // W of the block's eliminated columns as A fragments (row l % 16,
-    // column l/16 + 4u), through the wave's staging area
-    const bool elim = j0 + c < nelim;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) stage[c * SV_LDW + ga + 4 * q] = elim ? xv[q] : 0.0;
-    double af[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) af[u] = -stage[(4 * u + ga) * SV_LDW + c];
-    // later blocks of the panel: B fragment L'(16 cb' + l % 16, j0 + 4u + l/16)
-#pragma unroll
-    for (int cb = 1; cb < NBP; ++cb) {
-      if (cb <= b) continue;
-      const int jr = min(c0 + 16 * cb + c, p - 1);
-      double bf[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) bf[u] = lc[(size_t)min(j0 + 4 * u + ga, p - 1) * p + jr];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u], acc[cb], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < NBP; ++b) {
+    for (int q = 0; q < 4; ++q) v[q] = x[(size_t)j * ldx + rows[q]];
+  };
+  // a wave with rows below r stores all 16 of its rows: the rows past r
+  // (up to the next multiple of 16) are padding of x, whose leading
+  // dimension is r rounded up to a multiple of 32
+  const bool wave_rows = r0 < r;
+  auto store_x = [&](int b, const double* v) __attribute__((always_inline)) {
     const int j = c0 + 16 * b + c;
-    if (j >= p) continue;
+    if (wave_rows && j < p) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (rv[q]) x[(size_t)j * ldx + rows[q]] = acc[b][q];
+      for (int q = 0; q < 4; ++q) x[(size_t)j * ldx + r0 + ga + 4 * q] = v[q];
+    }
+  };
+  d4s acc[NBP];
+  double xn[4];
+  load_x(0, xn);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[0][q] = xn[q];
+#pragma unroll
+  for (int k = 1; k < NBP; ++k) acc[k] = d4s{0.0, 0.0, 0.0, 0.0};
+  fetch_l(0);
+  put_l(0);
+  for (int b = 0; b < nb; ++b) {
+    // block b's L' columns are in LDS (every thread's share); the other
+    // buffer was last read in the previous iteration
+    sv_lds_barrier();
+    const double* lb = lsh + (b & 1) * SV_LBUF;
+    if (b + 1 < nb) load_x(b + 1, xn);
+    if (b + 1 < nbe) fetch_l(b + 1);
+    double xv[4] = {acc[0][0], acc[0][1], acc[0][2], acc[0][3]};
+    if (b < nbe) {
+      const int j0 = c0 + 16 * b;
+      const int kkend = min(16, nelim - j0);
+      const unsigned zmask = (unsigned)__ballot((zb >> b) & 1u) & 0xffffu;
+      auto step = [&](auto kkc) __attribute__((always_inline)) {
+        constexpr int kk = decltype(kkc)::value;
+        if (kk >= kkend) return;
+        if ((zmask >> kk) & 1u) {
+          // a zero pivot: its column of L is zero
+#pragma unroll
+          for (int q = 0; q < 4; ++q) xv[q] = c == kk ? 0.0 : xv[q];
+        }
+        // L'(j0 + c, j0 + kk): zero above the diagonal, the unit diagonal
+        // itself must not update
+        const double lv = c == kk ? 0.0 : lb[kk * SV_LROWS + c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[q] = fma(-sv_share<kk>(xv[q]), lv, xv[q]);
+      };
+      step(std::integral_constant<int, 0>{});
+      step(std::integral_constant<int, 1>{});
+      step(std::integral_constant<int, 2>{});
+      step(std::integral_constant<int, 3>{});
+      step(std::integral_constant<int, 4>{});
+      step(std::integral_constant<int, 5>{});
+      step(std::integral_constant<int, 6>{});
+      step(std::integral_constant<int, 7>{});
+      step(std::integral_constant<int, 8>{});
+      step(std::integral_constant<int, 9>{});
+      step(std::integral_constant<int, 10>{});
+      step(std::integral_constant<int, 11>{});
+      step(std::integral_constant<int, 12>{});
+      step(std::integral_constant<int, 13>{});
+      step(std::integral_constant<int, 14>{});
+      step(std::integral_constant<int, 15>{});
+      if (b + 1 < nb) {
+        // W of the block's eliminated columns as A fragments (row l % 16,
+        // column l/16 + 4u), through the wave's staging area
+        const bool elim = j0 + c < nelim;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) stage[c * SV_LDW + ga + 4 * q] = elim ? xv[q] : 0.0;
+        double af[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) af[u] = -stage[(4 * u + ga) * SV_LDW + c];
+        // block b + k: B fragment L'(j0 + 16 k + l % 16, j0 + 4u + l/16)
+#pragma unroll
+        for (int k = 1; k < NBP; ++k) {
+          if (k >= nb - b) continue;
+          double bf[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bf[u] = lb[(4 * u + ga) * SV_LROWS + 16 * k + c];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u], acc[k], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k + 1 < NBP; ++k) acc[k] = acc[k + 1];
+    acc[NBP - 1] = d4s{0.0, 0.0, 0.0, 0.0};
+    if (b + 1 < nb) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[0][q] += xn[q];
+      // here, not after the stores below: a wait for X placed after them
+      // would wait for the stores too
+      asm volatile("" ::"v"(acc[0][0]), "v"(acc[0][1]), "v"(acc[0][2]), "v"(acc[0][3]) : "memory");
+    }
+    if (b + 1 < nbe) put_l(b + 1);
+    store_x(b, xv);
   }
 }
 
 template <int NBP>
 __global__ __launch_bounds__(256, 2) void solve_diag_kernel(int r, int p, int c0, const int* __restrict__ piv,
-                                                       const int* __restrict__ nelim_p, double* __restrict__ x,
-                                                       int ldx, const double* __restrict__ lc) {
+                                                          const int* __restrict__ nelim_p, double* __restrict__ x,
+                                                          int ldx, const double* __restrict__ lc) {
+  __shared__ double lsh[2 * SV_LBUF];
   __shared__ double stage[4][16 * SV_LDW];
   const int wave = threadIdx.x >> 6;
+  if ((int)blockIdx.x * 64 >= r) return;
+  // waves past the last row still take part in the staging and barriers
   const int r0 = (blockIdx.x * 4 + wave) * 16;
-  if (r0 >= r) return;
-  solve_diag_wave<NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, stage[wave], r0);
+  solve_diag_wg<NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, lsh, stage[wave], r0);
 }
 
 // Rows chunk*4096.. of column k: the workspace holds W (eliminated) or the
@@ -301,15 +367,18 @@ __global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode
 
 template <int NBP>
 __global__ __launch_bounds__(256, 2) void solve_diag_batch_kernel(const BatchNode* __restrict__ nodes, int method, int c0) {
+  __shared__ double lsh[2 * SV_LBUF];
   __shared__ double stage[4][16 * SV_LDW];
   const BatchNode& nd = nodes[blockIdx.y];
   const int r = nd.n - nd.p;
   const int wave = threadIdx.x >> 6;
+  if ((int)blockIdx.x * 64 >= r || c0 >= nd.p) return;
   const int r0 = (blockIdx.x * 4 + wave) * 16;
-  if (r0 >= r || c0 >= nd.p) return;
   const Workspace ws = workspace_layout(nd.n, nd.p, method);
-  solve_diag_wave<NBP>(r, nd.p, c0, nd.piv, min(max(*nd.nelim, 0), nd.p), reinterpret_cast<double*>(nd.work + ws.w_off),
-                       ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), stage[wave], r0);
+  // the node's panel may be narrower than NBP blocks: the extra blocks are
+  // past p (their columns are neither read nor written)
+  solve_diag_wg<NBP>(r, nd.p, c0, nd.piv, min(max(*nd.nelim, 0), nd.p), reinterpret_cast<double*>(nd.work + ws.w_off),
+                     ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), lsh, stage[wave], r0);
 }
 
 __global__ __launch_bounds__(256) void solve_scale_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
