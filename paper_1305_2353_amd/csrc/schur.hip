@@ -213,8 +213,6 @@ struct SchurWArgs {
   int ntm, ntn;
   int per_xcd;
   int tiled;           // 1: s is this tile's own 128 x 128 block (ld 128)
-  int rb = 0;          // rows of the second operand (0: r, as for W)
-  int ncol = 0;        // 0: lower triangle of the tile only; > 0: every column j < ncol
 };
 
 // Main loop and epilogue of one tile.  VEC: every row of both operands
@@ -272,7 +270,7 @@ __device__ __forceinline__ void schur_w_epilogue(const SchurWArgs& g, int i0, in
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wm * 64 + x * 16 + (TR ? lrow : lk + 4 * q);
         const int j = j0 + wn * 64 + y * 16 + (TR ? lk + 4 * q : lrow);
-        if (i < iend && (g.ncol ? j < g.ncol : j <= i)) {
+        if (i < iend && j <= i) {
           double* dst = g.tiled ? g.s + (size_t)(j - j0) * SC_BM + (i - i0)
                                 : g.s + (size_t)j * g.lds + (i - g.row0);
           if (VAR & 8) *dst -= acc[x][y][q];   // trailing update: C -= L21 W^T
@@ -421,7 +419,7 @@ __device__ __forceinline__ void schur_w_tile(const SchurWArgs& g, int i0, int j0
     const int oa = e < 2 ? ga + e : ga2 + (e - 2);
     const int ob = e < 2 ? gb + e : gb2 + (e - 2);
     rowa[e] = VEC ? oa : min(oa, g.r - 1);
-    rowb[e] = VEC ? ob : min(ob, (g.rb ? g.rb : g.r) - 1);
+    rowb[e] = VEC ? ob : min(ob, g.r - 1);
   }
 
   struct Stage {
@@ -798,109 +796,6 @@ int launch_schur_full(int n, int p, const double* a, int lda, const double* w, i
     if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
   }
   schur_persist_kernel<VAR><<<(unsigned)nwg, SC_THREADS, bytes, stream>>>(g, total, (int)(nwg / SC_NXCD), aligned);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
-}
-
-// ---------------------------------------------------------------------------
-// The Solve task's panel update (see solve.hip): X(:, c0:p) -= W(:, 0:c0)
-// L'(c0:p, 0:c0)^T, X and W the same workspace array (ld ldx), L' the
-// masked copy lc (ld p).  The Form's tile routine with the subtracting
-// epilogue and every column of the tile stored.
-// ---------------------------------------------------------------------------
-
-__host__ __device__ inline SchurWArgs solve_update_args(int r, int p, int c0, double* x, int ldx, const double* lc) {
-  SchurWArgs g;
-  g.r = r;
-  g.l21 = x;                 // A: W(:, k), k < c0
-  g.lda = ldx;
-  g.w = lc + c0;             // B: L'(c0 + j, k)
-  g.ldw = p;
-  g.nelim_p = nullptr;
-  g.p = c0;
-  g.row0 = 0;
-  g.nrows = r;
-  g.s = x + (size_t)c0 * ldx;
-  g.lds = ldx;
-  g.tiled = 0;
-  g.rb = p - c0;
-  g.ncol = p - c0;
-  g.ntm = (r + SC_BM - 1) / SC_BM;
-  g.ntn = (p - c0 + SC_BN - 1) / SC_BN;
-  g.per_xcd = 0;
-  return g;
-}
-
-template <int VAR>
-CTP_DEV void solve_update_tile(const SchurWArgs& g, int tm, int tn, int aligned) {
-  const int i0 = tm * SC_BM, j0 = tn * SC_BN;
-  if (aligned && i0 + SC_BM <= g.r && j0 + SC_BN <= g.rb) schur_w_tile<true, VAR>(g, i0, j0, g.p, sc_dyn);
-  else schur_w_tile<false, VAR>(g, i0, j0, g.p, sc_dyn);
-}
-
-template <int VAR>
-__global__ __launch_bounds__(SC_THREADS, 2) void solve_update_kernel(SchurWArgs g, int aligned) {
-  const int b = blockIdx.x;
-  const int tile = (b % SC_NXCD) * g.per_xcd + b / SC_NXCD;
-  if (tile >= g.ntm * g.ntn) return;
-  solve_update_tile<VAR>(g, tile / g.ntn, tile % g.ntn, aligned);
-}
-
-constexpr int SOLVE_UPDATE_VAR = 313;   // the Form's default schedule, subtracting
-
-template <typename K>
-static int solve_update_lds(K kern) {
-  constexpr int bytes = SchurWShape<SOLVE_UPDATE_VAR>::LDS_BYTES;
-  if (bytes > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       bytes);
-    if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
-  }
-  return 0;
-}
-
-int launch_solve_update(int r, int p, int c0, double* x, int ldx, const double* lc, hipStream_t stream) {
-  if (r <= 0 || c0 <= 0 || c0 >= p) return 0;
-  SchurWArgs g = solve_update_args(r, p, c0, x, ldx, lc);
-  const int total = g.ntm * g.ntn;
-  g.per_xcd = (total + SC_NXCD - 1) / SC_NXCD;
-  const int aligned = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(lc + c0)) % 16 == 0) &&
-                      ldx % 2 == 0 && p % 2 == 0;
-  int rc = solve_update_lds(solve_update_kernel<SOLVE_UPDATE_VAR>);
-  if (rc) return rc;
-  constexpr int bytes = SchurWShape<SOLVE_UPDATE_VAR>::LDS_BYTES;
-  solve_update_kernel<SOLVE_UPDATE_VAR><<<g.per_xcd * SC_NXCD, SC_THREADS, bytes, stream>>>(g, aligned);
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
-}
-
-// Batched: node blockIdx.y, tile blockIdx.x.
-template <int VAR>
-__global__ __launch_bounds__(SC_THREADS, 2) void solve_update_batch_kernel(const BatchNode* __restrict__ nodes,
-                                                                          int method, int c0) {
-  const BatchNode& nd = nodes[blockIdx.y];
-  const int r = nd.n - nd.p, p = nd.p;
-  if (r <= 0 || c0 >= p) return;
-  const int ntn = (p - c0 + SC_BN - 1) / SC_BN;
-  const int ntm = (r + SC_BM - 1) / SC_BM;
-  if ((int)blockIdx.x >= ntm * ntn) return;
-  const Workspace ws = workspace_layout(nd.n, nd.p, method);
-  double* x = reinterpret_cast<double*>(nd.work + ws.w_off);
-  const double* lc = reinterpret_cast<const double*>(nd.work + ws.lc_off);
-  const SchurWArgs g = solve_update_args(r, p, c0, x, ws.ldw, lc);
-  const int aligned = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(lc + c0)) % 16 == 0) &&
-                      ws.ldw % 2 == 0 && p % 2 == 0;
-  solve_update_tile<VAR>(g, blockIdx.x / ntn, blockIdx.x % ntn, aligned);
-}
-
-int launch_solve_update_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int c0,
-                              hipStream_t stream) {
-  if (count <= 0 || max_r <= 0 || c0 >= max_p) return 0;
-  int rc = solve_update_lds(solve_update_batch_kernel<SOLVE_UPDATE_VAR>);
-  if (rc) return rc;
-  constexpr int bytes = SchurWShape<SOLVE_UPDATE_VAR>::LDS_BYTES;
-  const dim3 grid(((max_r + SC_BM - 1) / SC_BM) * ((max_p - c0 + SC_BN - 1) / SC_BN), count);
-  solve_update_batch_kernel<SOLVE_UPDATE_VAR><<<grid, SC_THREADS, bytes, stream>>>(nodes, method, c0);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }

@@ -78,17 +78,17 @@ int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const 
 // go in panels of up to 256:
 //   gather   X into the workspace, L' (masked as above) into a compact
 //            p x p copy lc;
-//   diag     per panel: each wave takes 16 rows and solves them against the
-//            panel's diagonal block of L', right-looking in 16-column
-//            blocks held as FP64 matrix-core accumulators: forward
-//            substitution inside the 16 x 16 diagonal block (column kk
-//            broadcast to the lanes of its rows by a DPP row share), then
-//            the product with the block's W subtracted from the later
-//            blocks of the panel on the matrix cores.  No barriers: the
-//            waves of a workgroup are independent and many per CU hide the
-//            latency of the chain;
-//   update   between panels: X_2 -= W_1 L'_21^T, the Form's MFMA tile
-//            routine with a subtracting epilogue (schur.hip);
+//   diag     per panel: a workgroup of four waves takes 64 rows (16 per
+//            wave) and solves them against the panel's diagonal block of
+//            L', right-looking in 16-column blocks held as FP64
+//            matrix-core accumulators: forward substitution inside the
+//            16 x 16 diagonal block (column kk broadcast to the lanes of
+//            its rows by a DPP row share), then the product with the
+//            block's W subtracted from the later blocks of the panel on the
+//            matrix cores.  The columns of earlier panels enter first, as
+//            one product -W_1 L'_21^T into the same accumulators.  The L'
+//            columns a step needs are shared by the four waves through a
+//            double-buffered LDS copy;
 //   scale    L21 = W D^-1 into the panel (delayed columns copied
 //            unscaled), W kept in the workspace for the Form.
 // Every step is exact substitution or an exact product: the accuracy is
@@ -168,7 +168,8 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
   const int tid = threadIdx.x, lane = tid & 63;
   const int ga = lane >> 4, c = lane & 15;
   const int nbe = min(NBP, (nelim - c0 + 15) / 16);   // blocks of the panel with eliminated columns
-  if (nbe <= 0) return;                                // a panel of delayed columns: X is final
+  const int nkc = (min(c0, nelim) + 7) / 8;            // 8-column chunks of earlier eliminated columns
+  if (nbe <= 0 && nkc == 0) return;                    // nothing updates this panel: X is final
   const int nb = min(NBP, (p - c0 + 15) / 16);         // blocks with columns below p
   int rows[4];
 #pragma unroll
@@ -180,23 +181,31 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
   unsigned zb = 0;
 #pragma unroll
   for (int b = 0; b < NBP; ++b) zb |= (c0 + 16 * b + c < p && pv[b] == PIV_ZERO ? 1u : 0u) << b;
-  // L' staging: thread t carries column j0 + t/16, rows j0 + t%16 + 16 m
+  // L' staging: thread t carries column j0 + t/16, rows j0 + t%16 + 16 m.
+  // Rows and columns past p are clamped to p - 1: they only reach lanes and
+  // blocks of columns past p, which are never stored.
+  // A block is staged in two halves (m below or from NH), to halve the
+  // registers that carry it.
   const int skk = tid >> 4, si = tid & 15;
-  double lreg[NBP];
-  auto fetch_l = [&](int b) __attribute__((always_inline)) {
+  constexpr int NH = (NBP + 1) / 2;
+  double lreg[NH];
+  auto fetch_l = [&](int b, int half) __attribute__((always_inline)) {
     const int j0 = c0 + 16 * b;
     const int col = j0 + skk;
 #pragma unroll
-    for (int m = 0; m < NBP; ++m) {
+    for (int h = 0; h < NH; ++h) {
+      const int m = half * NH + h;
       const int row = j0 + si + 16 * m;
-      if (m < NBP - b) lreg[m] = row < p && col < p ? lc[(size_t)col * p + row] : 0.0;
+      if (m < NBP - b) lreg[h] = lc[(size_t)min(col, p - 1) * p + min(row, p - 1)];
     }
   };
-  auto put_l = [&](int b) __attribute__((always_inline)) {
+  auto put_l = [&](int b, int half) __attribute__((always_inline)) {
     double* buf = lsh + (b & 1) * SV_LBUF + skk * SV_LROWS + si;
 #pragma unroll
-    for (int m = 0; m < NBP; ++m)
-      if (m < NBP - b) buf[16 * m] = lreg[m];
+    for (int h = 0; h < NH; ++h) {
+      const int m = half * NH + h;
+      if (m < NBP - b) buf[16 * m] = lreg[h];
+    }
   };
   auto load_x = [&](int b, double* v) __attribute__((always_inline)) {
     const int j = min(c0 + 16 * b + c, p - 1);
@@ -215,21 +224,75 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
     }
   };
   d4s acc[NBP];
+#pragma unroll
+  for (int k = 0; k < NBP; ++k) acc[k] = d4s{0.0, 0.0, 0.0, 0.0};
+  if (nkc > 0) {
+    // the earlier panels' eliminated columns: acc[k] = -W(:, 0:8 nkc)
+    // L'(c0 + 16 k + :, 0:8 nkc)^T, eight columns at a time (thread t
+    // stages L' column 8 kc + t/32, rows c0 + t%32 + 32 m); A fragment u of
+    // lane l is W(row l % 16, column 8 kc + l/16 + 4u)
+    const int ra = min(r0 + c, r - 1);
+    const int ucol = tid >> 5, urow = tid & 31;
+    auto fetch_u = [&](int kc) __attribute__((always_inline)) {
+      const int col = 8 * kc + ucol;
+#pragma unroll
+      for (int m = 0; m < NH; ++m) {
+        const int row = c0 + urow + 32 * m;
+        lreg[m] = lc[(size_t)col * p + min(row, p - 1)];
+      }
+    };
+    auto put_u = [&](int kc) __attribute__((always_inline)) {
+      double* buf = lsh + (kc & 1) * SV_LBUF + ucol * SV_LROWS + urow;
+#pragma unroll
+      for (int m = 0; m < NH; ++m) buf[32 * m] = lreg[m];
+    };
+    auto load_a = [&](int kc, double* v) __attribute__((always_inline)) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) v[u] = x[(size_t)(8 * kc + ga + 4 * u) * ldx + ra];
+    };
+    double an[2];
+    load_a(0, an);
+    fetch_u(0);
+    put_u(0);
+    for (int kc = 0; kc < nkc; ++kc) {
+      sv_lds_barrier();
+      const double* lb = lsh + (kc & 1) * SV_LBUF;
+      const double af0 = -an[0], af1 = -an[1];
+      if (kc + 1 < nkc) {
+        load_a(kc + 1, an);
+        fetch_u(kc + 1);
+      }
+#pragma unroll
+      for (int k = 0; k < NBP; ++k) {
+        if (k >= nb) continue;
+        const double b0 = lb[ga * SV_LROWS + 16 * k + c];
+        const double b1 = lb[(4 + ga) * SV_LROWS + 16 * k + c];
+        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(af0, b0, acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(af1, b1, acc[k], 0, 0, 0);
+      }
+      if (kc + 1 < nkc) put_u(kc + 1);
+    }
+    // every wave is done with both buffers before the panel's own blocks
+    // are staged
+    sv_lds_barrier();
+  }
   double xn[4];
   load_x(0, xn);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[0][q] = xn[q];
-#pragma unroll
-  for (int k = 1; k < NBP; ++k) acc[k] = d4s{0.0, 0.0, 0.0, 0.0};
-  fetch_l(0);
-  put_l(0);
+  for (int q = 0; q < 4; ++q) acc[0][q] += xn[q];
+  if (nbe > 0) {
+    fetch_l(0, 0);
+    put_l(0, 0);
+    fetch_l(0, 1);
+    put_l(0, 1);
+  }
   for (int b = 0; b < nb; ++b) {
     // block b's L' columns are in LDS (every thread's share); the other
     // buffer was last read in the previous iteration
     sv_lds_barrier();
     const double* lb = lsh + (b & 1) * SV_LBUF;
     if (b + 1 < nb) load_x(b + 1, xn);
-    if (b + 1 < nbe) fetch_l(b + 1);
+    if (b + 1 < nbe) fetch_l(b + 1, 0);
     double xv[4] = {acc[0][0], acc[0][1], acc[0][2], acc[0][3]};
     if (b < nbe) {
       const int j0 = c0 + 16 * b;
@@ -268,6 +331,10 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
       if (b + 1 < nb) {
         // W of the block's eliminated columns as A fragments (row l % 16,
         // column l/16 + 4u), through the wave's staging area
+        if (b + 1 < nbe) {
+          put_l(b + 1, 0);
+          fetch_l(b + 1, 1);
+        }
         const bool elim = j0 + c < nelim;
 #pragma unroll
         for (int q = 0; q < 4; ++q) stage[c * SV_LDW + ga + 4 * q] = elim ? xv[q] : 0.0;
@@ -296,7 +363,7 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
       // would wait for the stores too
       asm volatile("" ::"v"(acc[0][0]), "v"(acc[0][1]), "v"(acc[0][2]), "v"(acc[0][3]) : "memory");
     }
-    if (b + 1 < nbe) put_l(b + 1);
+    if (b + 1 < nbe) put_l(b + 1, 1);
     store_x(b, xv);
   }
 }
@@ -390,9 +457,6 @@ __global__ __launch_bounds__(256) void solve_scale_batch_kernel(const BatchNode*
                    ws.ldw, blockIdx.y, blockIdx.x);
 }
 
-int launch_solve_update(int r, int p, int c0, double* x, int ldx, const double* lc, hipStream_t stream);
-int launch_solve_update_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int c0,
-                              hipStream_t stream);
 
 template <typename F>
 static void solve_diag_dispatch(int nbp, F&& f) {
@@ -409,10 +473,6 @@ int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* p
   solve_gather_kernel<<<cols, 256, 0, stream>>>(r, p, a, lda, perm, piv, nelim, w, ldw, lc);
   const unsigned grid = (unsigned)((r + 63) / 64);
   for (int c0 = 0; c0 < p; c0 += SV_PANEL) {
-    if (c0 > 0) {
-      int rc = launch_solve_update(r, p, c0, w, ldw, lc, stream);
-      if (rc) return rc;
-    }
     const int nbp = (min(SV_PANEL, p - c0) + 15) / 16;
     solve_diag_dispatch(nbp, [&](auto k) {
       constexpr int NBP = decltype(k)::value;
@@ -430,10 +490,6 @@ int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p,
   solve_gather_batch_kernel<<<cols, 256, 0, stream>>>(nodes, method);
   const dim3 grid((max_r + 63) / 64, count);
   for (int c0 = 0; c0 < max_p; c0 += SV_PANEL) {
-    if (c0 > 0) {
-      int rc = launch_solve_update_batch(count, nodes, method, max_p, max_r, c0, stream);
-      if (rc) return rc;
-    }
     const int nbp = (min(SV_PANEL, max_p - c0) + 15) / 16;
     solve_diag_dispatch(nbp, [&](auto k) {
       constexpr int NBP = decltype(k)::value;
