@@ -159,3 +159,76 @@ def dense_indefinite_batch_torch(S, N, seed=0, lam_lo=1e-2, nrhs=4, device="cuda
     A = 0.5 * (A + A.transpose(1, 2))
     B = torch.randn((S, N, nrhs), dtype=torch.float64, device=device, generator=g)
     return A, B
+
+
+def assembly_tree(seed=0, fanout=(3, 2), own_lo=16, own_hi=48, root_own=40, bound_frac=0.5,
+                  small_prob=0.05, small_scale=1e-8, bound_scale=1.0):
+    """A symmetric indefinite matrix with a known assembly tree.
+
+    Tree: a root whose nodes at depth d have fanout[d] children each (the
+    depth is len(fanout)).  Every non-root node owns own ~ U{own_lo..own_hi}
+    variables, the root owns root_own; variables are numbered in postorder
+    (a node's subtree before the node, children in order).  A node's
+    boundary is a random subset of its parent's front variables (the
+    parent's own variables and boundary), of size max(1, round(bound_frac *
+    that set)).  Entries: A[own, own] symmetric with G ~ N(0,1) reflected
+    from its lower triangle and each diagonal entry multiplied by
+    small_scale with probability small_prob (so that pivots fail and are
+    delayed); A[boundary, own] ~ bound_scale * N(0,1) and its transpose (a
+    large bound_scale makes the threshold test fail against the boundary
+    rows, so that every rule delays); zero elsewhere.
+
+    Draw order: own sizes (breadth first), then per node top-down the
+    boundary subset, then per node in postorder G, the small-diagonal mask,
+    the boundary block.
+
+    Returns a dict: A (N x N), parent (-1 for the root), children, own and
+    bound (int arrays of global variables), postorder (node ids, root last).
+    """
+    rng = np.random.default_rng(seed)
+    parent, children, depth = [-1], [[]], [0]
+    frontier = [0]
+    for d, f in enumerate(fanout):
+        nxt = []
+        for q in frontier:
+            for _ in range(f):
+                parent.append(q)
+                children.append([])
+                depth.append(d + 1)
+                children[q].append(len(parent) - 1)
+                nxt.append(len(parent) - 1)
+        frontier = nxt
+    nodes = len(parent)
+    size = [root_own] + [int(rng.integers(own_lo, own_hi + 1)) for _ in range(1, nodes)]
+    post = []
+
+    def visit(q):
+        for ch in children[q]:
+            visit(ch)
+        post.append(q)
+
+    visit(0)
+    own, start = [None] * nodes, 0
+    for q in post:
+        own[q] = np.arange(start, start + size[q])
+        start += size[q]
+    N = start
+    bound = [np.zeros(0, dtype=np.int64) for _ in range(nodes)]
+    for q in range(1, nodes):           # breadth first: a parent before its children
+        pool = np.concatenate([own[parent[q]], bound[parent[q]]])
+        k = max(1, int(round(bound_frac * pool.size)))
+        bound[q] = np.sort(rng.choice(pool, k, replace=False))
+    A = np.zeros((N, N))
+    for q in post:
+        o, b = own[q], bound[q]
+        G = rng.standard_normal((o.size, o.size))
+        B = np.tril(G) + np.tril(G, -1).T
+        mask = rng.random(o.size) < small_prob
+        B[mask, mask] *= small_scale
+        A[np.ix_(o, o)] = B
+        if b.size:
+            E = bound_scale * rng.standard_normal((b.size, o.size))
+            A[np.ix_(b, o)] = E
+            A[np.ix_(o, b)] = E.T
+    return {"A": A, "parent": parent, "children": children, "own": own, "bound": bound,
+            "postorder": post}
