@@ -81,6 +81,7 @@ extern "C" {
 #define CTP_STATUS_NONFINITE 2      /* a NaN/Inf was read by a pivot test or by the compression */
 #define CTP_STATUS_RELAXED_RESCAN 4 /* relaxed C needed a full column rescan */
 #define CTP_STATUS_ROOT_FALLBACK 8  /* CTP_FLAG_ROOT: a column was eliminated regardless of u */
+#define CTP_STATUS_BAD_MAP 16       /* extend-add: a map or perm entry out of range (entry skipped) */
 
 /* ctp_opts.flags bits. */
 #define CTP_FLAG_ROOT 1u   /* last panel of a factorization: eliminate every column
@@ -312,6 +313,66 @@ int ctp_solve_supernode_batched(int count, const ctp_node* nodes, const ctp_batc
 int ctp_schur_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, const double* panels,
                       const int* piv, const double* d, const int* nelim, double* s, const ctp_opts* opts,
                       void* work, size_t lwork, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Scatter (Section 1, the fourth task; delayed pivots move to a later
+ * supernode): extend-add of a factored front's contribution block into its
+ * parent front, for multifrontal chaining of the calls above.
+ *
+ * The child front has order n and p panel columns; after Factor + Solve its
+ * panel (ld lda) holds the delayed block (A11 rows, positions nelim..p-1,
+ * lower triangle) and the updated delayed columns (A21 rows), and the
+ * caller has formed its boundary block s = A22 - L21 D L21^T (n-p) x (n-p),
+ * lower triangle, ld lds: the Form with CTP_FLAG_S_SUBTRACT on the front's
+ * own trailing entries (zero when the boundary entries belong to ancestors).
+ * The contribution block is the trailing symmetric matrix over positions
+ * nelim..n-1.  Position t stands for the child's original local index
+ * v = perm[t] (t < p) or t (t >= p); map[v] (n ints, device) is its row in
+ * the parent front (order np, panel width pp, 1 <= pp <= np).  Entry
+ * (ti, tj), ti >= tj >= nelim, is added into the parent's lower triangle at
+ * (R, C) = (max, min)(map[v(ti)], map[v(tj)]): f[C*ldf + R] (the parent's
+ * np x pp panel) when C < pp, else f22[(C-pp)*ld22 + (R-pp)] (the parent's
+ * trailing (np-pp) x (np-pp) block, the input of its own Form with
+ * CTP_FLAG_S_SUBTRACT).  map must be injective on the positions read
+ * (entries of eliminated variables are not read); then every parent entry
+ * gets at most one add and the result does not depend on the schedule.
+ * An out-of-range map or perm entry skips that entry and ORs
+ * CTP_STATUS_BAD_MAP into *status (status may be NULL).  nelim and perm are
+ * device pointers (the factorization's outputs), so no host
+ * synchronization is needed.  Plain FP64 adds.
+ * ------------------------------------------------------------------------ */
+
+int ctp_extend_add(int n, int p, const double* a, int lda, const double* s, int lds, const int* perm,
+                   const int* nelim, const int* map, int np, int pp, double* f, int ldf, double* f22,
+                   int ld22, int* status, hipStream_t stream);
+
+/* One child of a batched extend-add; offsets in doubles (ints for map and
+ * perm) into the buffers of ctp_extend_add_batched. */
+typedef struct ctp_scatter_task {
+  int n, p, lda, lds;    /* child front, as for ctp_extend_add */
+  int np, pp, ldf, ld22; /* parent front */
+  int node;              /* the child's index into nelim[] */
+  long long a_off;       /* child panel: panels + a_off */
+  long long s_off;       /* child boundary block: s + s_off; -1 when n == p */
+  long long out_off;     /* child perm: perm + out_off */
+  long long map_off;     /* map + map_off (n ints) */
+  long long f_off;       /* parent panel: fpanels + f_off */
+  long long f22_off;     /* parent trailing block: f22 + f22_off; -1 when pp == np */
+  long long tile_off;    /* set by ctp_scatter_plan */
+} ctp_scatter_task;
+
+/* Host-side plan: checks tasks[count] (host memory), sets tile_off and
+ * *tiles (the launch size).  Errors: -(100 + k) for task k. */
+int ctp_scatter_plan(int count, ctp_scatter_task* tasks, long long* tiles);
+
+/* Extend-add of every task in one launch (tasks: device copy of the planned
+ * array).  No two tasks of one call may write the same parent entry (in a
+ * tree: at most one child per parent per call); several calls in stream
+ * order chain the children of a parent.  nelim: the child level's per-node
+ * outputs, indexed by task.node. */
+int ctp_extend_add_batched(int count, const ctp_scatter_task* tasks, long long tiles, const double* panels,
+                           const double* s, const int* perm, const int* nelim, const int* map,
+                           double* fpanels, double* f22, int* status, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Dense symmetric indefinite LDL^T from supernode panels (Section 1: the

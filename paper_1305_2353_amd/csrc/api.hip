@@ -38,6 +38,14 @@ int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p,
 int launch_schur_batch(int count, const BatchNode* nodes, int method, long long total, int tiled,
                        int subtract, unsigned int* counter, int variant, int workgroups, hipStream_t stream);
 
+int launch_extend_add(int n, int p, const double* a, int lda, const double* s, int lds, const int* perm,
+                      const int* nelim, const int* map, int np, int pp, double* f, int ldf, double* f22,
+                      int ld22, int* status, hipStream_t stream);
+long long scatter_tiles(int n);
+int launch_extend_add_batch(int count, const ctp_scatter_task* tasks, long long tiles, const double* panels,
+                            const double* s, const int* perm, const int* nelim, const int* map, double* fpanels,
+                            double* f22, int* status, hipStream_t stream);
+
 __global__ void clear_status_kernel(int* status) { *status = 0; }
 
 // Scratch of ctp_supernode_noalloc: one copy per GPU, held until the process
@@ -380,6 +388,59 @@ int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info
   rc = launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, stream);
   if (rc) return rc;
   return batch_form(count, info, s, opts, L, stream);
+}
+
+int ctp_extend_add(int n, int p, const double* a, int lda, const double* s, int lds, const int* perm,
+                   const int* nelim, const int* map, int np, int pp, double* f, int ldf, double* f22,
+                   int ld22, int* status, hipStream_t stream) {
+  if (n < 0) return -1;
+  if (p < 0 || p > n) return -2;
+  if (!a && p > 0) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (!s && n > p) return -5;
+  if (lds < (n - p > 1 ? n - p : 1)) return -6;
+  if (!perm && p > 0) return -7;
+  if (!nelim) return -8;
+  if (!map && n > 0) return -9;
+  if (np < 1) return -10;
+  if (pp < 1 || pp > np) return -11;
+  if (!f) return -12;
+  if (ldf < np) return -13;
+  if (!f22 && pp < np) return -14;
+  if (pp < np && ld22 < np - pp) return -15;
+  return launch_extend_add(n, p, a, lda, s, lds, perm, nelim, map, np, pp, f, ldf, f22, ld22, status, stream);
+}
+
+int ctp_scatter_plan(int count, ctp_scatter_task* tasks, long long* tiles) {
+  if (count < 0) return -1;
+  if (!tasks && count > 0) return -2;
+  if (!tiles) return -3;
+  long long total = 0;
+  for (int k = 0; k < count; ++k) {
+    ctp_scatter_task& t = tasks[k];
+    const bool ok = t.n >= 1 && t.p >= 0 && t.p <= t.n && t.lda >= t.n && t.node >= 0 && t.a_off >= 0 &&
+                    t.out_off >= 0 && t.map_off >= 0 && t.f_off >= 0 && t.np >= 1 && t.pp >= 1 &&
+                    t.pp <= t.np && t.ldf >= t.np &&
+                    (t.n == t.p || (t.s_off >= 0 && t.lds >= t.n - t.p)) &&
+                    (t.pp == t.np || (t.f22_off >= 0 && t.ld22 >= t.np - t.pp));
+    if (!ok) return -(100 + k);
+    t.tile_off = total;
+    total += scatter_tiles(t.n);
+  }
+  if (total > 0x7fffffffLL) return -4;
+  *tiles = total;
+  return 0;
+}
+
+int ctp_extend_add_batched(int count, const ctp_scatter_task* tasks, long long tiles, const double* panels,
+                           const double* s, const int* perm, const int* nelim, const int* map,
+                           double* fpanels, double* f22, int* status, hipStream_t stream) {
+  if (count < 0) return -1;
+  if (count == 0) return 0;
+  if (!tasks) return -2;
+  if (tiles < 0 || tiles > 0x7fffffffLL) return -3;
+  if (!panels || !perm || !nelim || !map || !fpanels) return -4;
+  return launch_extend_add_batch(count, tasks, tiles, panels, s, perm, nelim, map, fpanels, f22, status, stream);
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@ METHOD_IDS = {"tpp": CTP_TPP, "strict": CTP_STRICT, "relaxed": CTP_RELAXED,
 CTP_PIV_ZERO, CTP_PIV_1X1, CTP_PIV_2X2_FIRST, CTP_PIV_2X2_SECOND, CTP_PIV_DELAYED = 0, 1, 2, -2, -1
 CTP_STATUS_ZERO_PIVOT, CTP_STATUS_NONFINITE, CTP_STATUS_RELAXED_RESCAN = 1, 2, 4
 CTP_STATUS_ROOT_FALLBACK = 8
+CTP_STATUS_BAD_MAP = 16
 CTP_FLAG_ROOT = 1
 CTP_FLAG_ONE_WG = 2
 CTP_FLAG_S_TILED = 4
@@ -42,7 +43,7 @@ EXPORTED = ("ctp_default_opts", "ctp_version", "ctp_workspace_size", "ctp_compre
             "ctp_ldlt_adjoint", "ctp_batch_plan", "ctp_supernode_batched", "ctp_factor_supernode_batched",
             "ctp_solve_supernode_batched", "ctp_schur_batched",
             "ctp_dense_batched_workspace_size", "ctp_ldlt_dense_batched", "ctp_ldlt_solve_batched",
-            "ctp_ldlt_adjoint_batched")
+            "ctp_ldlt_adjoint_batched", "ctp_extend_add", "ctp_scatter_plan", "ctp_extend_add_batched")
 
 
 class CtpOpts(ctypes.Structure):
@@ -60,6 +61,14 @@ class CtpBatchInfo(ctypes.Structure):
     _fields_ = [("work_bytes", ctypes.c_size_t), ("tiles", ctypes.c_longlong), ("count", ctypes.c_int),
                 ("max_p", ctypes.c_int), ("max_r", ctypes.c_int), ("max_chunks", ctypes.c_int),
                 ("form_workgroups", ctypes.c_int)]
+
+
+class CtpScatterTask(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("lda", ctypes.c_int), ("lds", ctypes.c_int),
+                ("np", ctypes.c_int), ("pp", ctypes.c_int), ("ldf", ctypes.c_int), ("ld22", ctypes.c_int),
+                ("node", ctypes.c_int), ("a_off", ctypes.c_longlong), ("s_off", ctypes.c_longlong),
+                ("out_off", ctypes.c_longlong), ("map_off", ctypes.c_longlong), ("f_off", ctypes.c_longlong),
+                ("f22_off", ctypes.c_longlong), ("tile_off", ctypes.c_longlong)]
 
 
 class CtpError(RuntimeError):
@@ -106,6 +115,9 @@ def load(path=LIB_PATH):
         "ctp_ldlt_solve_batched": (I, [I, I, I, P, I, LL, P, P, P, P, I, LL, OPT, I, P, SZ, P]),
         "ctp_ldlt_adjoint_batched": (I, [I, I, I, P, I, LL, P, P, P, P, I, LL, P, I, LL, P, I, LL, OPT, I, P,
                                          SZ, P]),
+        "ctp_extend_add": (I, [I, I, P, I, P, I, P, P, P, I, I, P, I, P, I, P, P]),
+        "ctp_scatter_plan": (I, [I, P, ctypes.POINTER(LL)]),
+        "ctp_extend_add_batched": (I, [I, P, LL, P, P, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -556,3 +568,55 @@ class Batch:
                                         _ptr(self.piv), _ptr(self.d), _ptr(self.nelim), _ptr(self.S),
                                         ctypes.byref(self.opts), _ptr(self.work), self.work.numel(), _stream()),
                "ctp_schur_batched")
+
+
+# ---------------------------------------------------------------------------
+# Scatter (extend-add into the parent front)
+# ---------------------------------------------------------------------------
+
+def _colmajor(t, what):
+    if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2:
+        raise CtpError(f"{what} must be a 2-D float64 CUDA tensor")
+    rows, cols = t.shape
+    if cols > 1 and t.stride(0) != 1:
+        raise CtpError(f"{what} must be column-major (stride(0) == 1)")
+    return max(t.stride(1) if cols > 1 else rows, rows, 1)
+
+
+def ctp_extend_add(a, s, perm, nelim, vmap, f, f22=None, status=None):
+    """Add a factored front's contribution block into its parent front
+    (ctp_extend_add).  a: the child's n x p panel after Factor + Solve; s:
+    its (n-p) x (n-p) boundary block A22 - L21 D L21^T (None when n == p);
+    perm, nelim: the child's factorization outputs (int32 device tensors);
+    vmap: n int32 (child original local index -> parent row); f: the
+    parent's np x pp panel; f22: its (np-pp) x (np-pp) trailing block (None
+    when pp == np); status: optional int32 device word."""
+    n, p = a.shape
+    lda = _colmajor(a, "panel")
+    lds = _colmajor(s, "s") if s is not None else 1
+    np_, pp = f.shape
+    ldf = _colmajor(f, "parent panel")
+    ld22 = _colmajor(f22, "parent trailing block") if f22 is not None else 1
+    _check(load().ctp_extend_add(n, p, _ptr(a), lda, _ptr(s), lds, _ptr(perm), _ptr(nelim), _ptr(vmap), np_, pp,
+                                 _ptr(f), ldf, _ptr(f22), ld22, _ptr(status), _stream()), "ctp_extend_add")
+
+
+def ctp_scatter_plan(tasks):
+    """Plan a ctypes array of CtpScatterTask in place; returns the tiles."""
+    tiles = ctypes.c_longlong(0)
+    _check(load().ctp_scatter_plan(len(tasks), ctypes.cast(tasks, ctypes.c_void_p), ctypes.byref(tiles)),
+           "ctp_scatter_plan")
+    return tiles.value
+
+
+def ctp_extend_add_batched(tasks_dev, count, tiles, panels, s, perm, nelim, vmap, fpanels, f22, status=None):
+    """ctp_extend_add_batched on a device copy of a planned task array."""
+    _check(load().ctp_extend_add_batched(count, _ptr(tasks_dev), tiles, _ptr(panels), _ptr(s), _ptr(perm),
+                                         _ptr(nelim), _ptr(vmap), _ptr(fpanels), _ptr(f22), _ptr(status),
+                                         _stream()), "ctp_extend_add_batched")
+
+
+def to_device_struct(arr, device="cuda"):
+    """A ctypes structure array copied to device memory (uint8 tensor)."""
+    raw = bytes(memoryview(arr).cast("B"))
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
