@@ -159,3 +159,40 @@ def test_noalloc_rejects_panels_beyond_its_scratch(lib):
                                      None, 1, None) == ctp.CTP_ERR_SCRATCH_TOO_SMALL
     assert lib.ctp_supernode_noalloc(5, 10, fake, 5, ctypes.byref(o), fake, fake, fake, fake, fake, None, 1,
                                      None) == -1
+
+
+def test_scatter_argument_checks_and_plan(lib):
+    from paper_1305_2353_amd import ctp
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(4096)
+    # ctp_extend_add: shapes and leading dimensions checked on the host
+    assert lib.ctp_extend_add(10, 11, fake, 10, fake, 1, fake, fake, fake, 20, 5, fake, 20, fake, 15, None,
+                              nul) == -2
+    assert lib.ctp_extend_add(10, 4, fake, 9, fake, 6, fake, fake, fake, 20, 5, fake, 20, fake, 15, None,
+                              nul) == -4
+    assert lib.ctp_extend_add(10, 4, fake, 10, fake, 5, fake, fake, fake, 20, 5, fake, 20, fake, 15, None,
+                              nul) == -6
+    assert lib.ctp_extend_add(10, 4, fake, 10, fake, 6, fake, fake, fake, 20, 21, fake, 20, fake, 15, None,
+                              nul) == -11
+    assert lib.ctp_extend_add(10, 4, fake, 10, fake, 6, fake, fake, fake, 20, 5, fake, 19, fake, 15, None,
+                              nul) == -13
+    assert lib.ctp_extend_add(10, 4, fake, 10, fake, 6, fake, fake, fake, 20, 5, fake, 20, nul, 15, None,
+                              nul) == -14
+    assert lib.ctp_extend_add(10, 4, fake, 10, fake, 6, fake, fake, fake, 20, 5, fake, 20, fake, 14, None,
+                              nul) == -15
+    # the plan numbers 64 x 64 tiles of each child's lower triangle in order
+    tasks = (ctp.CtpScatterTask * 3)()
+    for t, (n, p) in zip(tasks, [(64, 10), (65, 65), (200, 30)]):
+        t.n, t.p, t.lda, t.lds = n, p, n, max(n - p, 1)
+        t.np, t.pp, t.ldf, t.ld22 = 300, 100, 300, 200
+        t.s_off = 0 if n > p else -1
+        t.f22_off = 0
+    assert ctp.ctp_scatter_plan(tasks) == 1 + 3 + 10
+    assert [t.tile_off for t in tasks] == [0, 1, 4]
+    tasks[2].lds = 169            # below n - p
+    with pytest.raises(ctp.CtpError, match="-102"):
+        ctp.ctp_scatter_plan(tasks)
+    tasks[2].lds = 170
+    tasks[1].f22_off = -1         # the parent has a trailing block
+    with pytest.raises(ctp.CtpError, match="-101"):
+        ctp.ctp_scatter_plan(tasks)
