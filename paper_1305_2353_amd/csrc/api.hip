@@ -25,6 +25,9 @@ int launch_schur_full(int n, int p, const double* a, int lda, const double* w, i
                       double* s, int lds, int tiled, int workgroups, hipStream_t stream);
 int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
                   const int* nelim, double* w, int ldw, hipStream_t stream);
+int launch_tpp_grid(int n, int p, double* a, int lda, int root, double u, double small, int* perm, int* piv,
+                    double* d, int* nelim, int* status, double* xt, int* pos, double* part, void* state,
+                    double* wbuf, double* xr, int ldr, hipStream_t stream);
 
 size_t batch_header_bytes(int count);
 int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags, double u, double small,
@@ -171,6 +174,12 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
   }
   const int root = (opts->flags & CTP_FLAG_ROOT) ? 1 : 0;
   const int one_wg = (opts->flags & CTP_FLAG_ONE_WG) ? 1 : 0;
+  if (method == CTP_TPP && r > 0 && !one_wg)
+    return launch_tpp_grid(n, p, a, lda, root, opts->u, opts->small, perm, piv, d, nelim, status,
+                           reinterpret_cast<double*>(base + ws.c_off), reinterpret_cast<int*>(base + ws.j_off),
+                           reinterpret_cast<double*>(base + ws.cand_off), base + ws.st_off,
+                           reinterpret_cast<double*>(base + ws.wb_off), reinterpret_cast<double*>(base + ws.w_off),
+                           ws.ldw, stream);
   return launch_pivot_factor(p, a, lda, rrows, R, ldr, abs_update, root, one_wg, opts->u, opts->small, perm,
                              piv, d, nelim, status, base + ws.st_off,
                              reinterpret_cast<double*>(base + ws.wb_off), stream);

@@ -45,12 +45,14 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block of the relaxed compression
 constexpr int PIV_NSLOT = 8;          // pending eliminated columns per batch of the pivot search
 constexpr int PIV_STATE_BYTES = 256;  // pivot-search state carried between launches
+constexpr int TPP_MAX_GROUPS_WS = 1024; // grid-wide TPP: workgroups of a step
+constexpr int TPP_PART_WS = 6;          // grid-wide TPP: doubles of partial maxima per workgroup
 
 // Workspace carve-up, shared by the size query and the launchers.
 struct Workspace {
-  size_t c_off = 0;       // p x p doubles: compressed matrix C
-  size_t j_off = 0;       // (n-p) ints: strict row -> set, relaxed scratch
-  size_t cand_off = 0;    // relaxed: per-chunk candidate keys
+  size_t c_off = 0;       // p x p doubles: compressed matrix C (TPP: working A11)
+  size_t j_off = 0;       // (n-p) ints: strict row -> set (TPP: p ints, variable -> position)
+  size_t cand_off = 0;    // relaxed: per-chunk candidate keys (TPP: per-workgroup maxima)
   size_t crow_off = 0;    // relaxed: p ints, A21 row behind each C row
   size_t st_off = 0;      // pivot-search state carried between launches
   size_t wb_off = 0;      // pivot-search batch of pivot-column values
@@ -93,9 +95,17 @@ __host__ __device__ inline Workspace workspace_layout(int n, int p, int method) 
   Workspace w;
   const int r = n > p ? n - p : 0;
   size_t off = 0;
-  if (method == CTP_STRICT || method == CTP_RELAXED) {
+  if (method == CTP_STRICT || method == CTP_RELAXED || method == CTP_TPP) {
+    // compressed: C; TPP: the working copy of A11
     w.c_off = off;
     off = align_up(off + (size_t)p * p * sizeof(double), 256);
+  }
+  if (method == CTP_TPP) {
+    // the grid-wide search: variable -> position, per-group column maxima
+    w.j_off = off;
+    off = align_up(off + (size_t)(p > 0 ? p : 1) * sizeof(int), 256);
+    w.cand_off = off;
+    off = align_up(off + (size_t)TPP_MAX_GROUPS_WS * TPP_PART_WS * sizeof(double), 256);
   }
   if (method == CTP_STRICT) {
     w.j_off = off;

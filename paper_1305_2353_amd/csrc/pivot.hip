@@ -52,6 +52,8 @@
 
 #pragma clang fp contract(off)
 
+#include "threshold_tests.h"
+
 namespace ctp {
 
 constexpr int PIV_MAX_THREADS = 1024;   // workgroup sizes 256, 512 or 1024 (template NT)
@@ -240,38 +242,6 @@ CTP_DEV void for_r_rows(int rc, int r, F&& f) {
   for (int i = rc + threadIdx.x; i < r; i += NT) f(i, std::false_type{});
 }
 
-struct Top2 {
-  double v1, v2;
-  bool bad;   // this thread met a NaN or an infinity (reported in the status word)
-};
-
-CTP_DEV Top2 top2_empty() { return Top2{-1.0, -1.0, false}; }
-
-// true for NaN and +-infinity
-CTP_DEV bool nonfinite(double x) { return !(fabs(x) <= 1.7976931348623157e308); }
-
-// x = |a| or NaN; a NaN never enters the maxima
-CTP_DEV void top2_insert(Top2& t, double x) {
-  t.bad |= nonfinite(x);
-  x = fmax(x, -1.0);
-  t.v2 = fmax(t.v2, fmin(t.v1, x));
-  t.v1 = fmax(t.v1, x);
-}
-
-CTP_DEV void top2_merge(Top2& t, double o1, double o2) {
-  t.v2 = fmax(fmax(t.v2, o2), fmin(t.v1, o1));
-  t.v1 = fmax(t.v1, o1);
-}
-
-CTP_DEV double top2_max(const Top2& t) { return t.v1 > 0.0 ? t.v1 : 0.0; }
-
-// largest value once one entry of value x is taken out (0 when none is left)
-CTP_DEV double top2_excluding(const Top2& t, double x) {
-  const double v = x == t.v1 ? t.v2 : t.v1;
-  return v > 0.0 ? v : 0.0;
-}
-
-CTP_DEV bool pv_better(double va, int ia, double vb, int ib) { return va > vb || (va == vb && ia < ib); }
 
 // The first entries a thread reads in a pass, loaded together before any is
 // used, so that one memory latency covers them (the scans below would
@@ -503,18 +473,6 @@ CTP_DEV void swap_rows(const PivotArgs& g, int ns, const SwapPlan& s) {
 
 enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT };
 
-// Non-singularity part of the 2x2 test alone (Section 2): the scaled
-// determinant is clear of cancellation and of small.
-CTP_DEV bool det_ok(double att, double atm, double amm, double small) {
-  const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
-  if (big < small) return false;
-  const double s = 1.0 / big;
-  const double det1 = (atm * s) * atm;
-  const double det0 = (amm * s) * att;
-  const double det = det0 - det1;
-  return fabs(det) > fmax(fmax(small, fabs(det0) / 2.0), fabs(det1) / 2.0);
-}
-
 // The pivot loop.  Its state (nelim, m, progress, the number of pending
 // slots) is uniform: every thread takes the same decisions from the same
 // reduced values and keeps its own copy, so a rejected candidate costs only
@@ -654,26 +612,7 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
         slot ^= 1;
         const double maxt = top2_excluding(ct, fabs(atm));    // rows other than t, m
         const double maxm2 = top2_excluding(cm, fabs(xtm));   // rows other than m, t
-        const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
-        bool ok = false;
-        if (!(big < g.small)) {
-          const double s = 1.0 / big;
-          const double det1 = (atm * s) * atm;
-          const double det0 = (amm * s) * att;
-          const double det = det0 - det1;
-          const double bound = fmax(fmax(g.small, fabs(det0) / 2.0), fabs(det1) / 2.0);
-          if (fabs(det) > bound) {
-            if (fmax(maxt, maxm2) < g.small) {
-              ok = true;
-            } else {
-              const double f = s / fabs(det);
-              const double gt = (f * fabs(amm)) * maxt + (f * fabs(atm)) * maxm2;
-              const double gm = (f * fabs(atm)) * maxt + (f * fabs(att)) * maxm2;
-              ok = (gt <= inv_u) && (gm <= inv_u);
-            }
-          }
-        }
-        if (ok) {
+        if (accept_2x2(att, atm, amm, maxt, maxm2, g.small, inv_u)) {
           action = ACT_2X2;
           d1 = att;
           d21 = atm;
@@ -704,14 +643,7 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
     const int s0 = ns;
     // 2x2 inverse (the same for every row)
     double i11 = 0.0, i21 = 0.0, i22 = 0.0;
-    if (two) {
-      const double s = 1.0 / fmax(fmax(fabs(d1), fabs(d21)), fabs(d2));
-      const double det = (d2 * s) * d1 - (d21 * s) * d21;
-      const double f = s / det;
-      i11 = f * d2;
-      i21 = -(f * d21);
-      i22 = f * d1;
-    }
+    if (two) inverse_2x2(d1, d21, d2, i11, i21, i22);
     // this thread's first cached R row: its interchange values are read
     // here, so that they travel with the square's (one memory round trip
     // for both halves of the column phase)
