@@ -33,13 +33,14 @@
 //   every workgroup, on its rows of A21:
 //     1. the multipliers of the slots the last decision added;
 //     2. a zero pivot's column cleared;
-//     3. a full batch applied to the uneliminated columns;
+//     3. a full batch applied to the uneliminated columns (the rows of the
+//        square take part in this step only);
 //     4. the candidate's column m and its partner column t scanned
 //        (largest two |a| of each, NaN / infinity seen);
 //   then the last-arriving workgroup:
 //     5. merges the partial maxima with those of the rows of A11, which it
-//        reads itself (A11 stays with the deciding workgroup: its
-//        interchanges, multipliers and batch updates are its own);
+//        reads itself (the square's interchanges and multipliers are the
+//        deciding workgroup's);
 //     6. takes the decision (zero, 2x2, 1x1 or reject) and records it;
 //     7. moves to the next candidate (new pass, end, or root fallback) and
 //        finds the partner of the new candidate along its row.
@@ -117,6 +118,43 @@ CTP_DEV double tpp_lazy(double v, const double* l, const TppState& S, const doub
     }
   }
   return v;
+}
+
+// The flush's columns and their pivot-column values, staged in LDS by the
+// workgroup (column j of the staged list is position nelim + j).
+__shared__ int tp_fcol[CTP_MAX_P];
+__shared__ double tp_fw[TPP_NSLOT][CTP_MAX_P];
+
+// As tpp_lazy, with the pivot-column values of staged column j.
+CTP_DEV double tpp_lazy_staged(double v, const double* l, const TppState& S, int j, int ns) {
+#pragma unroll
+  for (int s = 0; s < TPP_NSLOT; ++s) {
+    if (s >= ns) break;
+    const int kind = S.slot_kind[s];
+    if (kind == 1) {
+      const double prod = l[s] * tp_fw[s][j];
+      v = v - prod;
+    } else if (kind == 2 && s + 1 < TPP_NSLOT) {
+      const double upd = l[s] * tp_fw[s][j] + l[s + 1] * tp_fw[s + 1][j];
+      v = v - upd;
+    }
+  }
+  return v;
+}
+
+// A full batch on the uneliminated columns of one row (stride ld between
+// columns): eight columns' loads in flight at a time.
+CTP_DEV void tpp_flush_row(double* __restrict__ row, size_t ld, const double* l, const TppState& S, int q, int ns) {
+  constexpr int U = 8;
+  for (int j0 = 0; j0 < q; j0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j0 + u < q) v[u] = row[(size_t)tp_fcol[j0 + u] * ld];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (j0 + u < q) row[(size_t)tp_fcol[j0 + u] * ld] = tpp_lazy_staged(v[u], l, S, j0 + u, ns);
+  }
 }
 
 // Entry (i, c) of the A11 square, lazily (multipliers from the slots'
@@ -233,19 +271,6 @@ CTP_DEV int tpp_partner(const TppArgs& g, const TppState& S, int m, int ns, bool
   return g.perm[bi];
 }
 
-// Applies the batch [0, ns) to every uneliminated entry of the A11 square.
-// An entry's new value needs only itself and its row's multipliers, which
-// sit in eliminated columns the flush does not write: no ordering between
-// threads is needed.
-CTP_DEV void tpp_flush_t(const TppArgs& g, const TppState& S, int ns) {
-  const int p = g.p, q = p - S.nelim;
-  for (int e = threadIdx.x; e < q * q; e += TPP_THREADS) {
-    const int vi = g.perm[S.nelim + e % q], vc = g.perm[S.nelim + e / q];
-    g.xt[(size_t)vc * p + vi] = tpp_lazy_t(g, S, vi, vc, ns);
-  }
-  __syncthreads();
-}
-
 enum { TPP_NONE = 0, TPP_ZERO, TPP_2X2, TPP_1X1, TPP_REJECT };
 
 // Symmetric interchange of positions a and b (bookkeeping only).
@@ -349,7 +374,7 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
   TppState& S = tp_s;
   const int p = g.p;
   // the previous step consumed mat / zero / flush; after a flush the batch
-  // is empty (the square was flushed when it was requested)
+  // is empty (the grid applied it to the square and to A21)
   if (threadIdx.x == 0) {
     if (S.flush) {
       S.ns = 0;
@@ -437,11 +462,9 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
         S.ns = ns;
       }
       __syncthreads();
-      if (ns >= TPP_NSLOT - 1) {
-        tpp_flush_t(g, S, ns);
-        ns = 0;
-        if (threadIdx.x == 0) S.flush = 1;
-      }
+      // a full batch goes onto every uneliminated entry in the next step;
+      // until then the square is still read lazily with all its slots
+      if (ns >= TPP_NSLOT - 1 && threadIdx.x == 0) S.flush = 1;
     }
     __syncthreads();
     action = TPP_NONE;
@@ -502,12 +525,9 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
     return;
   }
   // end of the loop: the pending batch still has to reach the delayed
-  // columns (the square now, the rows of A21 in the finishing step)
-  if (ns > 0) {
-    tpp_flush_t(g, S, ns);
-    if (threadIdx.x == 0) S.flush = 1;
-  }
+  // columns (in the finishing step)
   if (threadIdx.x == 0) {
+    if (ns > 0) S.flush = 1;
     S.finishing = 1;
     S.scan = 0;
   }
@@ -552,12 +572,34 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
   __syncthreads();
   if (S.done) return;
   const int p = g.p;
-  const int i0 = blockIdx.x * g.rows_per_group, i1 = min(g.r, i0 + g.rows_per_group);
+  // rows: those of A21, then (for a batch) those of the square
+  const int i0 = blockIdx.x * g.rows_per_group, i1 = min(g.r + p, i0 + g.rows_per_group);
   const int ns = S.ns;                          // slots after this step's materialisation
   const int nsc = S.flush ? 0 : ns;             // pending for the scan
   const int vm = S.scan ? g.perm[S.m] : -1, vt = S.scan ? S.t : -1;
   Top2 cm = top2_empty(), ct = top2_empty();
+  const int q = p - S.nelim;   // uneliminated columns
+  if (S.flush) {
+    for (int j = threadIdx.x; j < q; j += TPP_THREADS) {
+      const int c = g.perm[S.nelim + j];
+      tp_fcol[j] = c;
+      for (int s = 0; s < ns; ++s) tp_fw[s][j] = g.w[s * p + c];
+    }
+    __syncthreads();
+  }
   for (int i = i0 + (int)threadIdx.x; i < i1; i += TPP_THREADS) {
+    if (i >= g.r) {
+      // a row of the square: only the batch, on its uneliminated entries
+      // (its multipliers were written when the slots were recorded)
+      const int vi = i - g.r;
+      if (!S.flush || g.pos[vi] < S.nelim) continue;
+      double* row = g.xt + vi;
+      double l[TPP_NSLOT];
+#pragma unroll
+      for (int s = 0; s < TPP_NSLOT; ++s) l[s] = s < ns ? row[(size_t)S.slot_var[s] * p] : 0.0;
+      tpp_flush_row(row, p, l, S, q, ns);
+      continue;
+    }
     double* row = g.xr + i;
     const int ldr = g.ldr;
     // multipliers of the slots materialised in earlier steps
@@ -592,12 +634,7 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
     // 2. a zero pivot's column
     if (S.zero_var >= 0) row[(size_t)S.zero_var * ldr] = 0.0;
     // 3. a full batch onto the uneliminated columns
-    if (S.flush) {
-      for (int j = S.nelim; j < p; ++j) {
-        const int c = g.perm[j];
-        row[(size_t)c * ldr] = tpp_lazy(row[(size_t)c * ldr], l, S, g.w, p, c, ns);
-      }
-    }
+    if (S.flush) tpp_flush_row(row, ldr, l, S, q, ns);
     // 4. the candidate's columns
     if (S.scan) {
       top2_insert(cm, fabs(tpp_lazy(row[(size_t)vm * ldr], l, S, g.w, p, vm, nsc)));
@@ -666,8 +703,8 @@ int launch_tpp_grid(int n, int p, double* a, int lda, int root, double u, double
   g.pos = pos;
   g.w = wbuf;
   g.part = part;
-  g.groups = std::max(1, std::min(TPP_MAX_GROUPS, (g.r + TPP_THREADS - 1) / TPP_THREADS));
-  g.rows_per_group = std::max(1, (g.r + g.groups - 1) / g.groups);
+  g.groups = std::max(1, std::min(TPP_MAX_GROUPS, (g.r + p + TPP_THREADS - 1) / TPP_THREADS));
+  g.rows_per_group = std::max(1, (g.r + p + g.groups - 1) / g.groups);
   g.root = root;
   g.u = u;
   g.small = small;
