@@ -45,7 +45,7 @@ __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a -
 constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block of the relaxed compression
 constexpr int PIV_NSLOT = 8;          // pending eliminated columns per batch of the pivot search
 constexpr int PIV_STATE_BYTES = 256;  // pivot-search state carried between launches
-constexpr int TPP_MAX_GROUPS_WS = 1024; // grid-wide TPP: workgroups of a step
+constexpr int TPP_MAX_GROUPS_WS = 4096; // grid-wide TPP: workgroups of a step (64 rows each)
 constexpr int TPP_PART_WS = 6;          // grid-wide TPP: doubles of partial maxima per workgroup
 
 // Workspace carve-up, shared by the size query and the launchers.
@@ -104,8 +104,8 @@ __host__ __device__ inline Workspace workspace_layout(int n, int p, int method) 
     // the grid-wide search: variable -> position, per-group column maxima
     w.j_off = off;
     off = align_up(off + (size_t)(p > 0 ? p : 1) * sizeof(int), 256);
-    w.cand_off = off;
-    off = align_up(off + (size_t)TPP_MAX_GROUPS_WS * TPP_PART_WS * sizeof(double), 256);
+    w.cand_off = off;   // then 64 ints of arrival counters
+    off = align_up(off + (size_t)TPP_MAX_GROUPS_WS * TPP_PART_WS * sizeof(double) + 64 * sizeof(int), 256);
   }
   if (method == CTP_STRICT) {
     w.j_off = off;

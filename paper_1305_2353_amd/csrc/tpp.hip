@@ -62,9 +62,11 @@ namespace ctp {
 
 constexpr int TPP_THREADS = 256;
 constexpr int TPP_WAVES = TPP_THREADS / 64;
+constexpr int TPP_ROWS = 64;   // rows of a workgroup
+constexpr int TPP_BUCKETS = 64; // first level of the arrival count
 constexpr int TPP_MAX_GROUPS = TPP_MAX_GROUPS_WS;
 constexpr int TPP_NSLOT = PIV_NSLOT;
-constexpr int TPP_PART = TPP_PART_WS;   // per group: v1, v2 of column m, v1, v2 of column t, bad
+constexpr int TPP_PART = TPP_PART_WS;   // per group: v1, v2 of column m, v1, v2 of column t, two bad flags
 
 struct TppState {
   int nelim, m, t, progress;       // m: candidate position; t: partner variable (-1: none)
@@ -87,7 +89,7 @@ struct TppArgs {
   int* pos;        // variable -> position
   double* w;       // TPP_NSLOT x p: pivot-column values of the slots, by variable
   double* part;    // groups x TPP_PART
-  int groups, rows_per_group;
+  int groups;      // workgroups of a step, TPP_ROWS rows each
   int root;
   double u, small;
   int* perm;       // position -> variable
@@ -142,18 +144,19 @@ CTP_DEV double tpp_lazy_staged(double v, const double* l, const TppState& S, int
   return v;
 }
 
-// A full batch on the uneliminated columns of one row (stride ld between
-// columns): eight columns' loads in flight at a time.
-CTP_DEV void tpp_flush_row(double* __restrict__ row, size_t ld, const double* l, const TppState& S, int q, int ns) {
+// A full batch on the staged columns [j0, j1) of one row (stride ld
+// between columns): eight columns' loads in flight at a time.
+CTP_DEV void tpp_flush_row(double* __restrict__ row, size_t ld, const double* l, const TppState& S, int j0, int j1,
+                           int ns) {
   constexpr int U = 8;
-  for (int j0 = 0; j0 < q; j0 += U) {
+  for (int jb = j0; jb < j1; jb += U) {
     double v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (j0 + u < q) v[u] = row[(size_t)tp_fcol[j0 + u] * ld];
+      if (jb + u < j1) v[u] = row[(size_t)tp_fcol[jb + u] * ld];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (j0 + u < q) row[(size_t)tp_fcol[j0 + u] * ld] = tpp_lazy_staged(v[u], l, S, j0 + u, ns);
+      if (jb + u < j1) row[(size_t)tp_fcol[jb + u] * ld] = tpp_lazy_staged(v[u], l, S, jb + u, ns);
   }
 }
 
@@ -181,6 +184,7 @@ __global__ void tpp_init_kernel(TppArgs g) {
     const int i = (int)(q % g.r), c = (int)(q / g.r);
     g.xr[(size_t)c * g.ldr + i] = CM(g.a, p + i, c, g.lda);
   }
+  if (tid < TPP_BUCKETS) reinterpret_cast<int*>(g.part + (size_t)TPP_MAX_GROUPS * TPP_PART)[tid] = 0;
   for (size_t k = tid; k < (size_t)p; k += stride) {
     g.perm[k] = (int)k;
     g.pos[k] = (int)k;
@@ -410,7 +414,7 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
       const double* pt = g.part + (size_t)q * TPP_PART;
       top2_merge(cmr, pt[0], pt[1]);
       top2_merge(ctr, pt[2], pt[3]);
-      cmr.bad |= pt[4] != 0.0;
+      cmr.bad |= pt[4] != 0.0 || pt[5] != 0.0;
     }
     // the rows of the square: column m over rows other than m, column t
     // over rows other than t
@@ -572,8 +576,10 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
   __syncthreads();
   if (S.done) return;
   const int p = g.p;
-  // rows: those of A21, then (for a batch) those of the square
-  const int i0 = blockIdx.x * g.rows_per_group, i1 = min(g.r + p, i0 + g.rows_per_group);
+  // 64 rows per workgroup, one per lane: those of A21, then (for a batch)
+  // those of the square.  The four waves share the rows and split a
+  // batch's columns; the scan's two columns go to waves 0 and 1.
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ns = S.ns;                          // slots after this step's materialisation
   const int nsc = S.flush ? 0 : ns;             // pending for the scan
   const int vm = S.scan ? g.perm[S.m] : -1, vt = S.scan ? S.t : -1;
@@ -587,32 +593,39 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
     }
     __syncthreads();
   }
-  for (int i = i0 + (int)threadIdx.x; i < i1; i += TPP_THREADS) {
-    if (i >= g.r) {
-      // a row of the square: only the batch, on its uneliminated entries
-      // (its multipliers were written when the slots were recorded)
-      const int vi = i - g.r;
-      if (!S.flush || g.pos[vi] < S.nelim) continue;
+  const int qs = (q + TPP_WAVES - 1) / TPP_WAVES;   // this wave's share of the batch's columns
+  const int qj0 = min(q, wave * qs), qj1 = min(q, qj0 + qs);
+  // blocks of 64 rows, grid-strided (the loop is uniform in the workgroup)
+  for (int base = blockIdx.x * TPP_ROWS; base < g.r + p; base += gridDim.x * TPP_ROWS) {
+  const int i = base + lane;
+  const bool rrow = i < g.r;
+  if (i >= g.r && i < g.r + p) {
+    // a row of the square: only the batch, on its uneliminated entries
+    // (its multipliers were written when the slots were recorded)
+    const int vi = i - g.r;
+    if (S.flush && g.pos[vi] >= S.nelim) {
       double* row = g.xt + vi;
       double l[TPP_NSLOT];
 #pragma unroll
       for (int s = 0; s < TPP_NSLOT; ++s) l[s] = s < ns ? row[(size_t)S.slot_var[s] * p] : 0.0;
-      tpp_flush_row(row, p, l, S, q, ns);
-      continue;
+      tpp_flush_row(row, p, l, S, qj0, qj1, ns);
     }
-    double* row = g.xr + i;
-    const int ldr = g.ldr;
+  }
+  double l[TPP_NSLOT];
+  double* row = g.xr + (rrow ? i : 0);
+  const int ldr = g.ldr;
+  if (rrow) {
     // multipliers of the slots materialised in earlier steps
     const int nold = S.mat_n ? S.mat_s0 : ns;
-    double l[TPP_NSLOT];
 #pragma unroll
     for (int s = 0; s < TPP_NSLOT; ++s) l[s] = s < nold ? row[(size_t)S.slot_var[s] * ldr] : 0.0;
-    // 1. multipliers of the new slot(s)
+    // 1. multipliers of the new slot(s): every wave computes them (the same
+    //    bits), wave 0 stores them
     if (S.mat_n == 1) {
       const int s0 = S.mat_s0, v = S.slot_var[s0];
       const double x = tpp_lazy(row[(size_t)v * ldr], l, S, g.w, p, v, s0);
       const double lv = x / S.slot_x[s0][0];
-      row[(size_t)v * ldr] = lv;
+      if (wave == 0) row[(size_t)v * ldr] = lv;
 #pragma unroll
       for (int s = 0; s < TPP_NSLOT; ++s)
         if (s == s0) l[s] = lv;
@@ -623,8 +636,10 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
       const double i11 = S.slot_x[s0][0], i21 = S.slot_x[s0][1], i22 = S.slot_x[s0 + 1][1];
       const double l1 = x1 * i11 + x2 * i21;
       const double l2 = x1 * i21 + x2 * i22;
-      row[(size_t)v1 * ldr] = l1;
-      row[(size_t)v2 * ldr] = l2;
+      if (wave == 0) {
+        row[(size_t)v1 * ldr] = l1;
+        row[(size_t)v2 * ldr] = l2;
+      }
 #pragma unroll
       for (int s = 0; s < TPP_NSLOT; ++s) {
         if (s == s0) l[s] = l1;
@@ -632,35 +647,56 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
       }
     }
     // 2. a zero pivot's column
-    if (S.zero_var >= 0) row[(size_t)S.zero_var * ldr] = 0.0;
-    // 3. a full batch onto the uneliminated columns
-    if (S.flush) tpp_flush_row(row, ldr, l, S, q, ns);
-    // 4. the candidate's columns
-    if (S.scan) {
-      top2_insert(cm, fabs(tpp_lazy(row[(size_t)vm * ldr], l, S, g.w, p, vm, nsc)));
-      if (vt >= 0) top2_insert(ct, fabs(tpp_lazy(row[(size_t)vt * ldr], l, S, g.w, p, vt, nsc)));
+    if (S.zero_var >= 0 && wave == 0) row[(size_t)S.zero_var * ldr] = 0.0;
+    // 3. a full batch onto this wave's share of the uneliminated columns
+    if (S.flush) tpp_flush_row(row, ldr, l, S, qj0, qj1, ns);
+  }
+  // the scan reads columns another wave may just have updated
+  if (S.flush) __syncthreads();
+  // 4. the candidate's columns
+  if (rrow && S.scan) {
+    if (wave == 0) top2_insert(cm, fabs(tpp_lazy(row[(size_t)vm * ldr], l, S, g.w, p, vm, nsc)));
+    if (wave == 1 && vt >= 0) top2_insert(ct, fabs(tpp_lazy(row[(size_t)vt * ldr], l, S, g.w, p, vt, nsc)));
+  }
+  }
+  if (S.scan && wave < 2) {
+    // wave 0 holds column m, wave 1 column t: each merges its own lanes
+    Top2 t = wave == 0 ? cm : ct;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o1 = __shfl_xor(t.v1, off, 64), o2 = __shfl_xor(t.v2, off, 64);
+      top2_merge(t, o1, o2);
+    }
+    const bool b = __any(t.bad);
+    if (lane == 0) {
+      double* pt = g.part + (size_t)blockIdx.x * TPP_PART + 2 * wave;
+      pt[0] = t.v1;
+      pt[1] = t.v2;
+      g.part[(size_t)blockIdx.x * TPP_PART + 4 + wave] = b ? 1.0 : 0.0;
     }
   }
-  if (S.scan) {
-    const Top2 rm = tpp_reduce_top2(cm, 0);
-    const Top2 rt = tpp_reduce_top2(ct, 1);
-    const bool b = tpp_any(cm.bad || ct.bad);
-    if (threadIdx.x == 0) {
-      double* pt = g.part + (size_t)blockIdx.x * TPP_PART;
-      pt[0] = rm.v1;
-      pt[1] = rm.v2;
-      pt[2] = rt.v1;
-      pt[3] = rt.v2;
-      pt[4] = b ? 1.0 : 0.0;
-    }
-  }
-  // the last workgroup to arrive decides
-  __threadfence();
+  // the last workgroup to arrive decides: first the last of each of up to
+  // TPP_BUCKETS buckets of workgroups, then the last of those.  The barrier
+  // orders the workgroup's writes before thread 0's device-scope fence (one
+  // fence per workgroup: on this GPU it writes back the XCD's L2).
   __syncthreads();
-  if (threadIdx.x == 0) tp_flag[1] = atomicAdd(&g.st->ticket, 1) == (int)gridDim.x - 1;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int nb = min(TPP_BUCKETS, (int)gridDim.x);
+    const int bucket = blockIdx.x % nb;
+    const int members = ((int)gridDim.x - bucket + nb - 1) / nb;
+    int* cnt = reinterpret_cast<int*>(g.part + (size_t)TPP_MAX_GROUPS * TPP_PART);
+    bool last = false;
+    if (atomicAdd(&cnt[bucket], 1) == members - 1) {
+      cnt[bucket] = 0;   // every member has arrived
+      __threadfence();
+      last = atomicAdd(&g.st->ticket, 1) == nb - 1;
+    }
+    tp_flag[1] = last;
+  }
   __syncthreads();
   if (!tp_flag[1]) return;
-  __threadfence();
+  if (threadIdx.x == 0) __threadfence();
+  __syncthreads();
   if (threadIdx.x == 0) S.ticket = 0;
   __syncthreads();
   tpp_decide(g);
@@ -703,8 +739,7 @@ int launch_tpp_grid(int n, int p, double* a, int lda, int root, double u, double
   g.pos = pos;
   g.w = wbuf;
   g.part = part;
-  g.groups = std::max(1, std::min(TPP_MAX_GROUPS, (g.r + p + TPP_THREADS - 1) / TPP_THREADS));
-  g.rows_per_group = std::max(1, (g.r + p + g.groups - 1) / g.groups);
+  g.groups = std::max(1, std::min(TPP_MAX_GROUPS, (g.r + p + TPP_ROWS - 1) / TPP_ROWS));
   g.root = root;
   g.u = u;
   g.small = small;
