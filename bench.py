@@ -37,12 +37,12 @@ BLOCK_ROWS = 4096
 
 # HBM bytes per Form launch from two rocprofv3 --pmc runs (FETCH_SIZE scaled by
 # the 1.9997 read factor measured on a plain copy of known size, WRITE_SIZE
-# unscaled): 2.409 GB read + 1.584 GB written on average over the 25 launches
+# unscaled): 2.357 GB read + 1.584 GB written on average over the 25 launches
 # of the n=100000, p=512 step, valid only for the kernel source they were
 # measured on.
 FORM_COUNTERS = {
-    "source_sha256": "ba551cc55bdbc8b9d4fa6c3984bd307281e7bb555c06459716e5941c777a88db",
-    "hbm_bytes_per_launch": 3939053633,
+    "source_sha256": "61ba35dedcdd09d3a868e22d4334ad70a18b478560680aeefb0bd3633e0d3daa",
+    "hbm_bytes_per_launch": 3940874583,
     "n": 100000, "p": 512,
 }
 
