@@ -116,10 +116,18 @@ typedef struct ctp_opts {
   int method;      /* CTP_TPP, CTP_STRICT, CTP_RELAXED or CTP_RESTRICTED */
   double u;        /* threshold, 0 < u <= 0.5 (Section 2; default 0.01) */
   double small;    /* entries below small count as zero (default 1e-20) */
-  int prec;        /* dense factorization only: trailing update in 0 = FP64,
-                      1 = FP32 matrix cores, 2 = BF16 matrix cores (FP32
-                      accumulation, FP32 trailing matrix); the supernode
-                      entry points always compute in FP64 */
+  int prec;        /* arithmetic of the Solve and the Form: 0 = FP64;
+                      1 = FP32 matrix cores; 2 = BF16 matrix-core operands.
+                      Both reduced modes accumulate in FP32; the pivot search,
+                      the 2x2 inverses and D^-1 stay FP64 (Factor is always
+                      FP64).  Supernode: ctp_solve_supernode (and the batched
+                      Solve) run the triangular solve with it and leave the
+                      reduced-precision operand rows of L21 and W at the end
+                      of the workspace; ctp_schur and the fused call form S
+                      from those (S stored as FP64; needs work).  The batched
+                      Form stays FP64.  Dense factorization: the panels'
+                      Solve and the trailing update, on an FP32 trailing
+                      matrix. */
   int tile;        /* Form kernel schedule variant (all give the same bits).
                       With a stored W: -1 or 0 = default (operands loaded
                       straight into a ring of four LDS buffers, 8 k per chunk,
@@ -140,8 +148,10 @@ void ctp_default_opts(ctp_opts* opts);
 const char* ctp_version(void);
 
 /* Bytes of device workspace that ctp_factor_supernode / ctp_supernode /
- * ctp_compress need for an n x p panel with opts->method; written to
- * *bytes.  The same workspace may be reused by later calls on the stream. */
+ * ctp_compress need for an n x p panel with opts->method (and, for
+ * opts->prec != 0, the reduced-precision operand rows of the Form); written
+ * to *bytes.  The same workspace may be reused by later calls on the
+ * stream. */
 int ctp_workspace_size(int n, int p, const ctp_opts* opts, size_t* bytes);
 
 /* Compression step alone (Section 4, Fig. 4.1 (a)-(b)): builds the p x p
@@ -189,6 +199,9 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
  * perm, piv, d, nelim are the device outputs of the factorization.  work:
  * the workspace sized by ctp_workspace_size for the same n, p and method
  * (it also holds the column-permuted A21 while the panel is overwritten).
+ * opts->prec 1 / 2: the triangular solve on the FP32 / BF16 matrix cores
+ * (FP32 substitution and accumulation, D^-1 and the 2x2 inverses FP64),
+ * then L21 and W converted for the reduced-precision Form.
  * Requires p <= CTP_MAX_P. */
 int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm,
                         const int* piv, const double* d, const int* nelim,
@@ -239,7 +252,10 @@ int ctp_supernode_noalloc(int n, int p, double* a, int lda, const ctp_opts* opts
  * ctp_workspace_size; then S = L21 W^T is formed from the stored W = L21 D
  * (the fast path).  Or work = NULL: W is formed from L21, piv and d inside
  * the kernel.  Errors: -14 when work is given and lwork is too small.
- * FP64 matrix-core arithmetic. */
+ * FP64 matrix-core arithmetic; with opts->prec 1 / 2 the product runs on the
+ * FP32 / BF16 matrix cores (FP32 accumulation, S stored as FP64) from the
+ * operand rows the reduced-precision Solve left in the workspace (work is
+ * then required: -13 without it). */
 int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
               const int* nelim, int row0, int nrows, double* s, int lds,
               const ctp_opts* opts, const void* work, size_t lwork, hipStream_t stream);

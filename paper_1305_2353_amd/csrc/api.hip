@@ -14,7 +14,7 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
                         int root, int one_wg, double u, double small, int* perm, int* piv, double* d,
                         int* nelim, int* status, void* state, double* wbuf, hipStream_t stream);
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv, const double* d,
-                 const int* nelim, double* w, int ldw, double* lc, hipStream_t stream);
+                 const int* nelim, double* w, int ldw, double* lc, int prec, hipStream_t stream);
 int launch_schur(int n, int p, const double* a, int lda, const int* piv, const double* d,
                  const int* nelim, int row0, int nrows, double* s, int lds, int tile,
                  hipStream_t stream);
@@ -25,6 +25,11 @@ int launch_schur_full(int n, int p, const double* a, int lda, const double* w, i
                       double* s, int lds, int tiled, int workgroups, hipStream_t stream);
 int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const double* d,
                   const int* nelim, double* w, int ldw, hipStream_t stream);
+int launch_lowp_convert(int r, int K, const double* l21, int lda, const double* w, int ldw, const int* nelim,
+                        int prec, void* ops, hipStream_t stream);
+int launch_lowp_form(int r, int K, const int* nelim, int row0, int nrows, double* s, int lds, int tiled, int prec,
+                     void* ops, hipStream_t stream);
+size_t lowp_ops_bytes(int r, int kmax);
 int launch_tpp_grid(int n, int p, double* a, int lda, int root, double u, double small, int* perm, int* piv,
                     double* d, int* nelim, int* status, double* xt, int* pos, double* part, void* state,
                     double* wbuf, double* xr, int ldr, hipStream_t stream);
@@ -37,7 +42,8 @@ int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags
 int launch_compress_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int max_chunks,
                           hipStream_t stream);
 int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipStream_t stream);
-int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream);
+int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int prec,
+                       hipStream_t stream);
 int launch_schur_batch(int count, const BatchNode* nodes, int method, long long total, int tiled,
                        int subtract, unsigned int* counter, int variant, int workgroups, hipStream_t stream);
 
@@ -81,11 +87,21 @@ static int noalloc_scratch(void** out) {
 
 static bool valid_method(int m) { return m >= CTP_TPP && m <= CTP_RESTRICTED; }
 
+// Supernode workspace: the layout of workspace_layout, then (prec FP32 /
+// BF16) the reduced-precision operand rows of L21 and W for the Form.
+static size_t lowp_region_off(const Workspace& ws) { return align_up(ws.total, 256); }
+static size_t supernode_work_bytes(int n, int p, const ctp_opts* o) {
+  const Workspace ws = workspace_layout(n, p, o->method);
+  if (o->prec == 0 || n <= p || p == 0) return ws.total;
+  return lowp_region_off(ws) + lowp_ops_bytes(n - p, p);
+}
+
 static int check_opts(const ctp_opts* o) {
   if (!o) return 1;
   if (!valid_method(o->method)) return 1;
   if (!(o->u > 0.0 && o->u <= 0.5)) return 1;
   if (!(o->small >= 0.0) || !std::isfinite(o->small)) return 1;
+  if (o->prec < 0 || o->prec > 2) return 1;
   return 0;
 }
 
@@ -113,7 +129,7 @@ int ctp_workspace_size(int n, int p, const ctp_opts* opts, size_t* bytes) {
   if (n < p) return -1;
   if (check_opts(opts)) return -3;
   if (!bytes) return -4;
-  *bytes = workspace_layout(n, p, opts->method).total;
+  *bytes = supernode_work_bytes(n, p, opts);
   return 0;
 }
 
@@ -198,11 +214,19 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const
   if (!nelim) return -8;
   if (check_opts(opts)) return -9;
   Workspace ws = workspace_layout(n, p, opts->method);
-  if (!work || lwork < ws.total) return -11;
-  double* w = reinterpret_cast<double*>(static_cast<unsigned char*>(work) + ws.w_off);
-  if (opts->method == CTP_TPP) return launch_form_w(n, p, a, lda, piv, d, nelim, w, ws.ldw, stream);
-  double* lc = reinterpret_cast<double*>(static_cast<unsigned char*>(work) + ws.lc_off);
-  return launch_solve(n, p, a, lda, perm, piv, d, nelim, w, ws.ldw, lc, stream);
+  if (!work || lwork < supernode_work_bytes(n, p, opts)) return -11;
+  unsigned char* base = static_cast<unsigned char*>(work);
+  double* w = reinterpret_cast<double*>(base + ws.w_off);
+  int rc;
+  if (opts->method == CTP_TPP) {
+    rc = launch_form_w(n, p, a, lda, piv, d, nelim, w, ws.ldw, stream);
+  } else {
+    double* lc = reinterpret_cast<double*>(base + ws.lc_off);
+    rc = launch_solve(n, p, a, lda, perm, piv, d, nelim, w, ws.ldw, lc, opts->prec, stream);
+  }
+  if (rc || opts->prec == 0 || n <= p || p == 0) return rc;
+  // the Form's operand rows in reduced precision
+  return launch_lowp_convert(n - p, p, a + p, lda, w, ws.ldw, nelim, opts->prec, base + lowp_region_off(ws), stream);
 }
 
 int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
@@ -217,6 +241,9 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* p
   if (rc) return rc == -11 ? -13 : rc;
   if (!s || r <= 0 || p == 0) return 0;
   Workspace ws = workspace_layout(n, p, opts->method);
+  if (opts->prec != 0)
+    return launch_lowp_form(r, p, nelim, 0, r, s, lds, tiled ? 1 : 0, opts->prec,
+                            static_cast<unsigned char*>(work) + lowp_region_off(ws), stream);
   const double* w = reinterpret_cast<const double*>(static_cast<const unsigned char*>(work) + ws.w_off);
   return launch_schur_full(n, p, a, lda, w, ws.ldw, nelim, s, lds, tiled ? 1 : 0, 0, stream);
 }
@@ -226,7 +253,7 @@ int ctp_supernode_noalloc(int n, int p, double* a, int lda, const ctp_opts* opts
   if (n < p) return -1;
   if (p < 0) return -2;
   if (check_opts(opts)) return -5;
-  const size_t need = workspace_layout(n, p, opts->method).total;
+  const size_t need = supernode_work_bytes(n, p, opts);
   if (need > CTP_NOALLOC_SCRATCH_BYTES) return CTP_ERR_SCRATCH_TOO_SMALL;
   void* work = nullptr;
   int rc = noalloc_scratch(&work);
@@ -250,6 +277,16 @@ int ctp_schur(int n, int p, const double* a, int lda, const int* piv, const doub
   if (!s && nrows > 0) return -10;
   if (lds < (nrows > 1 ? nrows : 1)) return -11;
   if (check_opts(opts)) return -12;
+  if (opts->prec != 0) {
+    // reduced precision: the operand rows the Solve converted
+    if (!work) return -13;
+    if (lwork < supernode_work_bytes(n, p, opts)) return -14;
+    if (nrows == 0) return 0;
+    const Workspace ws = workspace_layout(n, p, opts->method);
+    return launch_lowp_form(n - p, p, nelim, row0, nrows, s, lds, 0, opts->prec,
+                            const_cast<unsigned char*>(static_cast<const unsigned char*>(work)) + lowp_region_off(ws),
+                            stream);
+  }
   if (work) {
     Workspace ws = workspace_layout(n, p, opts->method);
     if (lwork < ws.total) return -14;
@@ -367,7 +404,7 @@ int ctp_solve_supernode_batched(int count, const ctp_node* nodes, const ctp_batc
   rc = launch_batch_setup(count, nodes, opts->method, opts->flags, opts->u, opts->small, panels, nullptr, pm, pv, dd,
                           ne, ne, work, &L.bn, &L.pargs, &L.counter, 0, stream);
   if (rc) return rc;
-  return launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, stream);
+  return launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, opts->prec, stream);
 }
 
 int ctp_schur_batched(int count, const ctp_node* nodes, const ctp_batch_info* info, const double* panels,
@@ -394,7 +431,7 @@ int ctp_supernode_batched(int count, const ctp_node* nodes, const ctp_batch_info
   BatchLaunch L;
   rc = batch_factor(count, nodes, info, panels, s, perm, piv, d, nelim, status, opts, work, L, stream);
   if (rc) return rc;
-  rc = launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, stream);
+  rc = launch_solve_batch(count, L.bn, opts->method, info->max_p, info->max_r, opts->prec, stream);
   if (rc) return rc;
   return batch_form(count, info, s, opts, L, stream);
 }

@@ -17,10 +17,11 @@
 // The host reads back nelim after each panel (panel widths depend on it).
 //
 // Reduced precision (ctp_opts.prec 1 / 2): the trailing matrix lives in an
-// FP32 copy, the trailing update runs on FP32 / BF16 matrix cores with FP32
-// accumulation, while the panels (pivot search, 2x2 inverses, L21, W) are
-// computed in FP64 from the FP32 trailing values.  The solve uses the FP64
-// factors; refinement computes residuals with the original FP64 matrix.
+// FP32 copy; each panel's triangular solve (L21, W) and the trailing update
+// run on FP32 / BF16 matrix cores with FP32 accumulation, from operand rows
+// the solve converts once; the pivot search, the 2x2 inverses and D^-1 stay
+// FP64 (on the FP32 trailing values).  The solve with the factors is FP64;
+// refinement computes residuals with the original FP64 matrix.
 //
 // Solve with the factors, P A P^T = L D L^T:
 //   y = P b;  L y' = y (forward);  z = D^-1 y';  L^T x' = z (backward);
@@ -42,9 +43,8 @@ namespace ctp {
 
 int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, int ldw,
                        const int* nelim, double* c, int ldc, hipStream_t stream);
-int launch_lowp_update(int r, int K, const double* l21, int lda, const double* w, int ldw,
-                       const int* nelim, float* c, int ldc, int prec, void* ops, hipStream_t stream);
-size_t lowp_ops_bytes(int r, int kmax);
+int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops,
+                           hipStream_t stream);
 
 constexpr int DB = 128;   // diagonal block of the solve
 
@@ -530,7 +530,6 @@ struct DenseWork {
   size_t linv_off = 0, linvt_off = 0;  // inverses of the diagonal blocks
   size_t w32_off = 0;                  // FP32 trailing matrix (reduced precision)
   int ld32 = 0;
-  size_t ops_off = 0;                  // low-precision operands of the trailing update
   size_t y_off = 0;                    // solve / refinement vectors
   size_t arow_off = 0;                 // absolute row sums of A (refinement)
   size_t norms_off = 0;
@@ -562,7 +561,6 @@ static DenseWork dense_layout(int N, int pw, const ctp_opts* o, int nrhs_max) {
   if (o->prec != 0) {
     w.ld32 = (int)align_up((size_t)N, 64);
     w.w32_off = off; off = align_up(off + (size_t)w.ld32 * N * sizeof(float), 256);
-    w.ops_off = off; off = align_up(off + lowp_ops_bytes(N, pmax), 256);
   }
   w.y_off = off; off = align_up(off + (size_t)3 * N * (nrhs_max > 0 ? nrhs_max : 1) * sizeof(double), 256);
   w.arow_off = off; off = align_up(off + (size_t)(N > 0 ? N : 1) * sizeof(double), 256);
@@ -694,9 +692,11 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
         rc = launch_schur_w_sub(n, width, ap, lda, w, ws.ldw, pnelim,
                                 a + (size_t)(k0 + width) * lda + (k0 + width), lda, stream);
       } else {
-        rc = launch_lowp_update(n - width, ne, ap + width, lda, w, ws.ldw, pnelim,
-                                w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width), L.ld32, opts->prec,
-                                base + L.ops_off, stream);
+        // the operand rows of L21 and W that the reduced-precision Solve
+        // converted into the supernode workspace
+        rc = launch_lowp_update_ops(n - width, width, pnelim, w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width),
+                                    L.ld32, opts->prec, static_cast<unsigned char*>(sn) + align_up(ws.total, 256),
+                                    stream);
       }
       if (rc) return rc;
     }

@@ -21,6 +21,11 @@
 //    of C and the read-modify-write of C touches 64-byte runs (with L21 as
 //    the A operand the rows of a lane group were 4 apart).
 
+// The same product serves the supernode Form in reduced precision (opts
+// prec fp32 / bf16): S = L21 W^T stored as FP64 into rows row0..row0+nrows-1
+// of the lower triangle (column-major, or as the 128 x 128 tiles of
+// CTP_FLAG_S_TILED), from operand rows the Solve converted once.
+
 #include "common.h"
 
 namespace ctp {
@@ -73,13 +78,16 @@ struct LowpArgs {
   int kcap;
   const void* a;     // L21 rows
   const void* b;     // W rows
-  float* c;
+  float* c;          // trailing update: C -= L21 W^T (FP32)
   int ldc;
-  int nt;            // tiles per side
+  double* s;         // Form: S = L21 W^T (FP64), rows row0..row0+nrows-1
+  int lds, tiled, row0, nrows;
+  int ntm, ntn;      // tiles down and across
   int per_xcd;
 };
 
-template <typename T>
+// FORM = false: the dense trailing update; true: the supernode Form.
+template <typename T, bool FORM>
 __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) {
   constexpr int LP_BK = LowpTraits<T>::BK;
   constexpr int EPV = 16 / sizeof(T);            // elements per 16-byte vector
@@ -91,16 +99,17 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
 
   const int bid = blockIdx.x;
   const int tile = (bid % LP_NXCD) * g.per_xcd + bid / LP_NXCD;
-  const int total = g.nt * g.nt;
+  const int total = g.ntm * g.ntn;
   if (tile >= total) return;
-  const int per_group = LP_GROUP * g.nt;
+  const int per_group = LP_GROUP * g.ntn;
   const int grp = tile / per_group;
   const int in_grp = tile % per_group;
-  const int gm = min(LP_GROUP, g.nt - grp * LP_GROUP);
+  const int gm = min(LP_GROUP, g.ntm - grp * LP_GROUP);
   const int tm = grp * LP_GROUP + in_grp % gm;
   const int tn = in_grp / gm;
-  const int i0 = tm * LP_BM, j0 = tn * LP_BM;
-  if (j0 > i0) return;   // strictly above the diagonal
+  const int i0 = g.row0 + tm * LP_BM, j0 = tn * LP_BM;
+  if (j0 > i0 + LP_BM - 1) return;   // strictly above the diagonal
+  const int iend = FORM ? g.row0 + g.nrows : g.r;   // rows of this call
 
   const int K = min(max(*g.nelim_p, 0), g.kcap);
   const int nk = (K + LP_BK - 1) / LP_BK;
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
     for (int h = 0; h < NV; ++h) {
       const int q = tid + h * LP_THREADS;
       const int row = q / VPR, kv = q % VPR;
-      const int ia = min(i0 + row, g.r - 1), ib = min(j0 + row, g.r - 1);
+      const int ia = min(i0 + row, iend - 1), ib = min(j0 + row, g.r - 1);
       const size_t ko = (size_t)kc * LP_BK + kv * EPV;
       ra[h] = *reinterpret_cast<const u4*>(A + (size_t)ia * g.kp + ko);
       rb[h] = *reinterpret_cast<const u4*>(B + (size_t)ib * g.kp + ko);
@@ -191,40 +200,89 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
       for (int q = 0; q < 4; ++q) {
         const int i = i0 + wm * 64 + x * 16 + lrow;
         const int j = j0 + wn * 64 + y * 16 + 4 * lk + q;
-        if (i < g.r && j <= i) g.c[(size_t)j * g.ldc + i] -= acc[x][y][q];
+        if (i < iend && j <= i) {
+          if (!FORM) {
+            g.c[(size_t)j * g.ldc + i] -= acc[x][y][q];
+          } else if (g.tiled) {
+            const size_t ti = (size_t)(i / LP_BM) * (i / LP_BM + 1) / 2 + j / LP_BM;
+            g.s[ti * LP_BM * LP_BM + (size_t)(j % LP_BM) * LP_BM + i % LP_BM] = (double)acc[x][y][q];
+          } else {
+            g.s[(size_t)j * g.lds + (i - g.row0)] = (double)acc[x][y][q];
+          }
+        }
       }
 }
 
-int launch_lowp_update(int r, int K, const double* l21, int lda, const double* w, int ldw,
-                       const int* nelim, float* c, int ldc, int prec, void* ops, hipStream_t stream) {
+// Operand rows (k contiguous, K padded to LP_KPAD) of L21 and W in ops, in
+// FP32 (prec 1) or BF16 (prec 2).
+int launch_lowp_convert(int r, int K, const double* l21, int lda, const double* w, int ldw, const int* nelim,
+                        int prec, void* ops, hipStream_t stream) {
   if (r <= 0 || K <= 0) return 0;
   const int kp = (int)align_up((size_t)K, LP_KPAD);
   const size_t half = align_up((size_t)r * kp * sizeof(float), 256);
   void* opa = ops;
   void* opb = static_cast<unsigned char*>(ops) + half;
   const dim3 cg((r + 63) / 64, kp / 64);
-  LowpArgs g;
+  if (prec == 1) {
+    lowp_convert_kernel<float><<<cg, 256, 0, stream>>>(l21, lda, r, nelim, K, static_cast<float*>(opa), kp);
+    lowp_convert_kernel<float><<<cg, 256, 0, stream>>>(w, ldw, r, nelim, K, static_cast<float*>(opb), kp);
+  } else {
+    lowp_convert_kernel<__bf16><<<cg, 256, 0, stream>>>(l21, lda, r, nelim, K, static_cast<__bf16*>(opa), kp);
+    lowp_convert_kernel<__bf16><<<cg, 256, 0, stream>>>(w, ldw, r, nelim, K, static_cast<__bf16*>(opb), kp);
+  }
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+static LowpArgs lowp_args(int r, int K, const int* nelim, void* ops) {
+  const int kp = (int)align_up((size_t)K, LP_KPAD);
+  const size_t half = align_up((size_t)r * kp * sizeof(float), 256);
+  LowpArgs g{};
   g.r = r;
   g.kp = kp;
   g.nelim_p = nelim;
   g.kcap = K;
-  g.a = opa;
-  g.b = opb;
+  g.a = ops;
+  g.b = static_cast<unsigned char*>(ops) + half;
+  return g;
+}
+
+// The trailing update from operand rows already converted (by
+// launch_lowp_convert with the same r and K).
+int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops,
+                           hipStream_t stream) {
+  if (r <= 0 || K <= 0) return 0;
+  LowpArgs g = lowp_args(r, K, nelim, ops);
   g.c = c;
   g.ldc = ldc;
-  g.nt = (r + LP_BM - 1) / LP_BM;
-  const int total = g.nt * g.nt;
+  g.ntm = g.ntn = (r + LP_BM - 1) / LP_BM;
+  const int total = g.ntm * g.ntn;
   g.per_xcd = (total + LP_NXCD - 1) / LP_NXCD;
   const unsigned grid = g.per_xcd * LP_NXCD;
-  if (prec == 1) {
-    lowp_convert_kernel<float><<<cg, 256, 0, stream>>>(l21, lda, r, nelim, K, static_cast<float*>(opa), kp);
-    lowp_convert_kernel<float><<<cg, 256, 0, stream>>>(w, ldw, r, nelim, K, static_cast<float*>(opb), kp);
-    lowp_update_kernel<float><<<grid, LP_THREADS, 0, stream>>>(g);
-  } else {
-    lowp_convert_kernel<__bf16><<<cg, 256, 0, stream>>>(l21, lda, r, nelim, K, static_cast<__bf16*>(opa), kp);
-    lowp_convert_kernel<__bf16><<<cg, 256, 0, stream>>>(w, ldw, r, nelim, K, static_cast<__bf16*>(opb), kp);
-    lowp_update_kernel<__bf16><<<grid, LP_THREADS, 0, stream>>>(g);
-  }
+  if (prec == 1) lowp_update_kernel<float, false><<<grid, LP_THREADS, 0, stream>>>(g);
+  else lowp_update_kernel<__bf16, false><<<grid, LP_THREADS, 0, stream>>>(g);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+}
+
+// Supernode Form in reduced precision from the converted operand rows: rows
+// row0..row0+nrows-1 of S (tiled: row0 a multiple of 128).
+int launch_lowp_form(int r, int K, const int* nelim, int row0, int nrows, double* s, int lds, int tiled, int prec,
+                     void* ops, hipStream_t stream) {
+  if (r <= 0 || K <= 0 || nrows <= 0) return 0;
+  LowpArgs g = lowp_args(r, K, nelim, ops);
+  g.s = s;
+  g.lds = lds;
+  g.tiled = tiled;
+  g.row0 = row0;
+  g.nrows = nrows;
+  g.ntm = (nrows + LP_BM - 1) / LP_BM;
+  g.ntn = (row0 + nrows + LP_BM - 1) / LP_BM;
+  const int total = g.ntm * g.ntn;
+  g.per_xcd = (total + LP_NXCD - 1) / LP_NXCD;
+  const unsigned grid = g.per_xcd * LP_NXCD;
+  if (prec == 1) lowp_update_kernel<float, true><<<grid, LP_THREADS, 0, stream>>>(g);
+  else lowp_update_kernel<__bf16, true><<<grid, LP_THREADS, 0, stream>>>(g);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }

@@ -15,6 +15,7 @@
 namespace ctp {
 
 typedef double d4s __attribute__((ext_vector_type(4)));
+typedef float f4s __attribute__((ext_vector_type(4)));
 
 // 2x2 pivot inverse entries, scaled as in the pivot search.
 CTP_DEV void inv2x2(double a11, double a21, double a22, double& i11, double& i21, double& i22) {
@@ -137,6 +138,51 @@ CTP_DEV double sv_share(double x) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+template <int K>
+CTP_DEV float sv_share(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), SV_ROW_SHARE + K, 0xf, 0xf, true));
+}
+
+// Arithmetic of the diagonal-panel kernel, by precision (opts.prec).
+// 0, FP64: the FP64 matrix cores (v_mfma_f64_16x16x4f64); accumulator
+//    element q of lane l is row l/16 + 4q, column l % 16.
+// 1, FP32: X and L' rounded to FP32, the substitution in FP32, the products
+//    on the FP32 matrix cores (v_mfma_f32_16x16x4f32, the same operand
+//    fragments as FP64: lane l holds A(l % 16, k0 + l/16), B(k0 + l/16,
+//    l % 16)); accumulator element q of lane l is row 4(l/16) + q, column
+//    l % 16.
+// 2, BF16: as FP32, but the products take BF16 operands
+//    (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation: lane l holds A(l % 16,
+//    4(l/16) + v) and B(4(l/16) + v, l % 16), v = 0..3).
+// X is read from and written to the FP64 workspace in every case.
+typedef short s4s __attribute__((ext_vector_type(4)));
+typedef __bf16 b4s __attribute__((ext_vector_type(4)));
+
+template <int PREC> struct SvArith;
+template <> struct SvArith<0> {
+  using T = double;
+  using acc_t = d4s;
+  static CTP_DEV int row(int ga, int q) { return ga + 4 * q; }
+  static CTP_DEV acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct SvArith<1> {
+  using T = float;
+  using acc_t = f4s;
+  static CTP_DEV int row(int ga, int q) { return 4 * ga + q; }
+  static CTP_DEV acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <> struct SvArith<2> {
+  using T = float;
+  using acc_t = f4s;
+  static CTP_DEV int row(int ga, int q) { return 4 * ga + q; }
+  static CTP_DEV acc_t mma16(const float* a, const float* b, acc_t c) {
+    const b4s ab = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3]};
+    const b4s bb = {(__bf16)b[0], (__bf16)b[1], (__bf16)b[2], (__bf16)b[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4s, ab), __builtin_bit_cast(s4s, bb), c, 0,
+                                                      0, 0);
+  }
+};
+
 // LDS of the diagonal-panel kernel: the 16 columns of L' of the current
 // block (rows from the block's first column to the end of the panel), two
 // buffers, and a transposition area per wave.  Entry (row j0 + i, column j0
@@ -162,9 +208,13 @@ CTP_DEV void sv_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier"
 // through registers (fetched at the start of an iteration, written to LDS
 // at its end): the memory traffic is spread over the whole loop and hidden
 // behind the arithmetic of the current block.
-template <int NBP>
+template <int PREC, int NBP>
 CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, int nelim, double* __restrict__ x,
-                           int ldx, const double* __restrict__ lc, double* lsh, double* stage, int r0) {
+                           int ldx, const double* __restrict__ lc, typename SvArith<PREC>::T* lsh,
+                           typename SvArith<PREC>::T* stage, int r0) {
+  using A = SvArith<PREC>;
+  using T = typename A::T;
+  using acc_t = typename A::acc_t;
   const int tid = threadIdx.x, lane = tid & 63;
   const int ga = lane >> 4, c = lane & 15;
   const int nbe = min(NBP, (nelim - c0 + 15) / 16);   // blocks of the panel with eliminated columns
@@ -173,7 +223,7 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
   const int nb = min(NBP, (p - c0 + 15) / 16);         // blocks with columns below p
   int rows[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) rows[q] = min(r0 + ga + 4 * q, r - 1);
+  for (int q = 0; q < 4; ++q) rows[q] = min(r0 + A::row(ga, q), r - 1);
   // bit b: column c0 + 16 b + c has a zero pivot
   int pv[NBP];
 #pragma unroll
@@ -188,7 +238,7 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
   // registers that carry it.
   const int skk = tid >> 4, si = tid & 15;
   constexpr int NH = (NBP + 1) / 2;
-  double lreg[NH];
+  T lreg[NH];
   auto fetch_l = [&](int b, int half) __attribute__((always_inline)) {
     const int j0 = c0 + 16 * b;
     const int col = j0 + skk;
@@ -196,36 +246,36 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
     for (int h = 0; h < NH; ++h) {
       const int m = half * NH + h;
       const int row = j0 + si + 16 * m;
-      if (m < NBP - b) lreg[h] = lc[(size_t)min(col, p - 1) * p + min(row, p - 1)];
+      if (m < NBP - b) lreg[h] = (T)lc[(size_t)min(col, p - 1) * p + min(row, p - 1)];
     }
   };
   auto put_l = [&](int b, int half) __attribute__((always_inline)) {
-    double* buf = lsh + (b & 1) * SV_LBUF + skk * SV_LROWS + si;
+    T* buf = lsh + (b & 1) * SV_LBUF + skk * SV_LROWS + si;
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
       const int m = half * NH + h;
       if (m < NBP - b) buf[16 * m] = lreg[h];
     }
   };
-  auto load_x = [&](int b, double* v) __attribute__((always_inline)) {
+  auto load_x = [&](int b, T* v) __attribute__((always_inline)) {
     const int j = min(c0 + 16 * b + c, p - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = x[(size_t)j * ldx + rows[q]];
+    for (int q = 0; q < 4; ++q) v[q] = (T)x[(size_t)j * ldx + rows[q]];
   };
   // a wave with rows below r stores all 16 of its rows: the rows past r
   // (up to the next multiple of 16) are padding of x, whose leading
   // dimension is r rounded up to a multiple of 32
   const bool wave_rows = r0 < r;
-  auto store_x = [&](int b, const double* v) __attribute__((always_inline)) {
+  auto store_x = [&](int b, const T* v) __attribute__((always_inline)) {
     const int j = c0 + 16 * b + c;
     if (wave_rows && j < p) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) x[(size_t)j * ldx + r0 + ga + 4 * q] = v[q];
+      for (int q = 0; q < 4; ++q) x[(size_t)j * ldx + r0 + A::row(ga, q)] = (double)v[q];
     }
   };
-  d4s acc[NBP];
+  acc_t acc[NBP];
 #pragma unroll
-  for (int k = 0; k < NBP; ++k) acc[k] = d4s{0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < NBP; ++k) acc[k] = acc_t{0, 0, 0, 0};
   if (nkc > 0) {
     // the earlier panels' eliminated columns: acc[k] = -W(:, 0:8 nkc)
     // L'(c0 + 16 k + :, 0:8 nkc)^T, eight columns at a time (thread t
@@ -238,26 +288,34 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
 #pragma unroll
       for (int m = 0; m < NH; ++m) {
         const int row = c0 + urow + 32 * m;
-        lreg[m] = lc[(size_t)col * p + min(row, p - 1)];
+        lreg[m] = (T)lc[(size_t)col * p + min(row, p - 1)];
       }
     };
     auto put_u = [&](int kc) __attribute__((always_inline)) {
-      double* buf = lsh + (kc & 1) * SV_LBUF + ucol * SV_LROWS + urow;
+      T* buf = lsh + (kc & 1) * SV_LBUF + ucol * SV_LROWS + urow;
 #pragma unroll
       for (int m = 0; m < NH; ++m) buf[32 * m] = lreg[m];
     };
-    auto load_a = [&](int kc, double* v) __attribute__((always_inline)) {
+    // BF16 takes 16 k per product: the lanes with l/16 < 2 carry the
+    // chunk's eight columns (4(l/16) + v), the others zeros
+    constexpr int NA = PREC == 2 ? 4 : 2;
+    auto load_a = [&](int kc, T* v) __attribute__((always_inline)) {
 #pragma unroll
-      for (int u = 0; u < 2; ++u) v[u] = x[(size_t)(8 * kc + ga + 4 * u) * ldx + ra];
+      for (int u = 0; u < NA; ++u) {
+        if (PREC == 2) v[u] = ga < 2 ? (T)x[(size_t)(8 * kc + 4 * ga + u) * ldx + ra] : (T)0;
+        else v[u] = (T)x[(size_t)(8 * kc + ga + 4 * u) * ldx + ra];
+      }
     };
-    double an[2];
+    T an[NA];
     load_a(0, an);
     fetch_u(0);
     put_u(0);
     for (int kc = 0; kc < nkc; ++kc) {
       sv_lds_barrier();
-      const double* lb = lsh + (kc & 1) * SV_LBUF;
-      const double af0 = -an[0], af1 = -an[1];
+      const T* lb = lsh + (kc & 1) * SV_LBUF;
+      T af[NA];
+#pragma unroll
+      for (int u = 0; u < NA; ++u) af[u] = -an[u];
       if (kc + 1 < nkc) {
         load_a(kc + 1, an);
         fetch_u(kc + 1);
@@ -265,10 +323,17 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
 #pragma unroll
       for (int k = 0; k < NBP; ++k) {
         if (k >= nb) continue;
-        const double b0 = lb[ga * SV_LROWS + 16 * k + c];
-        const double b1 = lb[(4 + ga) * SV_LROWS + 16 * k + c];
-        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(af0, b0, acc[k], 0, 0, 0);
-        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(af1, b1, acc[k], 0, 0, 0);
+        if constexpr (PREC == 2) {
+          T bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bv[u] = ga < 2 ? lb[(4 * ga + u) * SV_LROWS + 16 * k + c] : (T)0;
+          acc[k] = A::mma16(af, bv, acc[k]);
+        } else {
+          const T b0 = lb[ga * SV_LROWS + 16 * k + c];
+          const T b1 = lb[(4 + ga) * SV_LROWS + 16 * k + c];
+          acc[k] = A::mma(af[0], b0, acc[k]);
+          acc[k] = A::mma(af[1], b1, acc[k]);
+        }
       }
       if (kc + 1 < nkc) put_u(kc + 1);
     }
@@ -276,7 +341,7 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
     // are staged
     sv_lds_barrier();
   }
-  double xn[4];
+  T xn[4];
   load_x(0, xn);
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[0][q] += xn[q];
@@ -290,10 +355,10 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
     // block b's L' columns are in LDS (every thread's share); the other
     // buffer was last read in the previous iteration
     sv_lds_barrier();
-    const double* lb = lsh + (b & 1) * SV_LBUF;
+    const T* lb = lsh + (b & 1) * SV_LBUF;
     if (b + 1 < nb) load_x(b + 1, xn);
     if (b + 1 < nbe) fetch_l(b + 1, 0);
-    double xv[4] = {acc[0][0], acc[0][1], acc[0][2], acc[0][3]};
+    T xv[4] = {acc[0][0], acc[0][1], acc[0][2], acc[0][3]};
     if (b < nbe) {
       const int j0 = c0 + 16 * b;
       const int kkend = min(16, nelim - j0);
@@ -304,11 +369,11 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
         if ((zmask >> kk) & 1u) {
           // a zero pivot: its column of L is zero
 #pragma unroll
-          for (int q = 0; q < 4; ++q) xv[q] = c == kk ? 0.0 : xv[q];
+          for (int q = 0; q < 4; ++q) xv[q] = c == kk ? (T)0 : xv[q];
         }
         // L'(j0 + c, j0 + kk): zero above the diagonal, the unit diagonal
         // itself must not update
-        const double lv = c == kk ? 0.0 : lb[kk * SV_LROWS + c];
+        const T lv = c == kk ? (T)0 : lb[kk * SV_LROWS + c];
 #pragma unroll
         for (int q = 0; q < 4; ++q) xv[q] = fma(-sv_share<kk>(xv[q]), lv, xv[q]);
       };
@@ -337,25 +402,33 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
         }
         const bool elim = j0 + c < nelim;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) stage[c * SV_LDW + ga + 4 * q] = elim ? xv[q] : 0.0;
-        double af[4];
+        for (int q = 0; q < 4; ++q) stage[c * SV_LDW + A::row(ga, q)] = elim ? xv[q] : (T)0;
+        // (BF16: row l % 16, columns 4(l/16) + v)
+        T af[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) af[u] = -stage[(4 * u + ga) * SV_LDW + c];
+        for (int u = 0; u < 4; ++u)
+          af[u] = PREC == 2 ? -stage[(4 * ga + u) * SV_LDW + c] : -stage[(4 * u + ga) * SV_LDW + c];
         // block b + k: B fragment L'(j0 + 16 k + l % 16, j0 + 4u + l/16)
+        // (BF16: L'(j0 + 16 k + l % 16, j0 + 4(l/16) + v))
 #pragma unroll
         for (int k = 1; k < NBP; ++k) {
           if (k >= nb - b) continue;
-          double bf[4];
+          T bf[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) bf[u] = lb[(4 * u + ga) * SV_LROWS + 16 * k + c];
+          for (int u = 0; u < 4; ++u)
+            bf[u] = PREC == 2 ? lb[(4 * ga + u) * SV_LROWS + 16 * k + c] : lb[(4 * u + ga) * SV_LROWS + 16 * k + c];
+          if constexpr (PREC == 2) {
+            acc[k] = A::mma16(af, bf, acc[k]);
+          } else {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[u], acc[k], 0, 0, 0);
+            for (int u = 0; u < 4; ++u) acc[k] = A::mma(af[u], bf[u], acc[k]);
+          }
         }
       }
     }
 #pragma unroll
     for (int k = 0; k + 1 < NBP; ++k) acc[k] = acc[k + 1];
-    acc[NBP - 1] = d4s{0.0, 0.0, 0.0, 0.0};
+    acc[NBP - 1] = acc_t{0, 0, 0, 0};
     if (b + 1 < nb) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[0][q] += xn[q];
@@ -368,17 +441,18 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
   }
 }
 
-template <int NBP>
+template <int PREC, int NBP>
 __global__ __launch_bounds__(256, 2) void solve_diag_kernel(int r, int p, int c0, const int* __restrict__ piv,
                                                           const int* __restrict__ nelim_p, double* __restrict__ x,
                                                           int ldx, const double* __restrict__ lc) {
-  __shared__ double lsh[2 * SV_LBUF];
-  __shared__ double stage[4][16 * SV_LDW];
+  using T = typename SvArith<PREC>::T;
+  __shared__ T lsh[2 * SV_LBUF];
+  __shared__ T stage[4][16 * SV_LDW];
   const int wave = threadIdx.x >> 6;
   if ((int)blockIdx.x * 64 >= r) return;
   // waves past the last row still take part in the staging and barriers
   const int r0 = (blockIdx.x * 4 + wave) * 16;
-  solve_diag_wg<NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, lsh, stage[wave], r0);
+  solve_diag_wg<PREC, NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, lsh, stage[wave], r0);
 }
 
 // Rows chunk*4096.. of column k: the workspace holds W (eliminated) or the
@@ -432,10 +506,11 @@ __global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode
                     ws.ldw, reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y, blockIdx.x);
 }
 
-template <int NBP>
+template <int PREC, int NBP>
 __global__ __launch_bounds__(256, 2) void solve_diag_batch_kernel(const BatchNode* __restrict__ nodes, int method, int c0) {
-  __shared__ double lsh[2 * SV_LBUF];
-  __shared__ double stage[4][16 * SV_LDW];
+  using T = typename SvArith<PREC>::T;
+  __shared__ T lsh[2 * SV_LBUF];
+  __shared__ T stage[4][16 * SV_LDW];
   const BatchNode& nd = nodes[blockIdx.y];
   const int r = nd.n - nd.p;
   const int wave = threadIdx.x >> 6;
@@ -444,7 +519,7 @@ __global__ __launch_bounds__(256, 2) void solve_diag_batch_kernel(const BatchNod
   const Workspace ws = workspace_layout(nd.n, nd.p, method);
   // the node's panel may be narrower than NBP blocks: the extra blocks are
   // past p (their columns are neither read nor written)
-  solve_diag_wg<NBP>(r, nd.p, c0, nd.piv, min(max(*nd.nelim, 0), nd.p), reinterpret_cast<double*>(nd.work + ws.w_off),
+  solve_diag_wg<PREC, NBP>(r, nd.p, c0, nd.piv, min(max(*nd.nelim, 0), nd.p), reinterpret_cast<double*>(nd.work + ws.w_off),
                      ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), lsh, stage[wave], r0);
 }
 
@@ -465,8 +540,11 @@ static void solve_diag_dispatch(int nbp, F&& f) {
   else f(std::integral_constant<int, 16>{});
 }
 
+// prec 0: FP64 throughout; 1 / 2: the triangular solve in FP32 on the FP32 /
+// BF16 matrix cores (FP32 accumulation); the gather, the 2x2 inverses and
+// D^-1 stay FP64.
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv, const double* d,
-                 const int* nelim, double* w, int ldw, double* lc, hipStream_t stream) {
+                 const int* nelim, double* w, int ldw, double* lc, int prec, hipStream_t stream) {
   const int r = n - p;
   if (r <= 0 || p <= 0) return 0;
   const dim3 cols((r + 4095) / 4096, p);
@@ -476,7 +554,9 @@ int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* p
     const int nbp = (min(SV_PANEL, p - c0) + 15) / 16;
     solve_diag_dispatch(nbp, [&](auto k) {
       constexpr int NBP = decltype(k)::value;
-      solve_diag_kernel<NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
+      if (prec == 1) solve_diag_kernel<1, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
+      else if (prec == 2) solve_diag_kernel<2, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
+      else solve_diag_kernel<0, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
     });
   }
   solve_scale_kernel<<<cols, 256, 0, stream>>>(r, p, a, lda, piv, d, nelim, w, ldw);
@@ -484,7 +564,8 @@ int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* p
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
 
-int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, hipStream_t stream) {
+int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p, int max_r, int prec,
+                       hipStream_t stream) {
   if (count <= 0 || max_r <= 0 || max_p <= 0) return 0;
   const dim3 cols((max_r + 4095) / 4096, max_p, count);
   solve_gather_batch_kernel<<<cols, 256, 0, stream>>>(nodes, method);
@@ -493,7 +574,9 @@ int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p,
     const int nbp = (min(SV_PANEL, max_p - c0) + 15) / 16;
     solve_diag_dispatch(nbp, [&](auto k) {
       constexpr int NBP = decltype(k)::value;
-      solve_diag_batch_kernel<NBP><<<grid, 256, 0, stream>>>(nodes, method, c0);
+      if (prec == 1) solve_diag_batch_kernel<1, NBP><<<grid, 256, 0, stream>>>(nodes, method, c0);
+      else if (prec == 2) solve_diag_batch_kernel<2, NBP><<<grid, 256, 0, stream>>>(nodes, method, c0);
+      else solve_diag_batch_kernel<0, NBP><<<grid, 256, 0, stream>>>(nodes, method, c0);
     });
   }
   solve_scale_batch_kernel<<<cols, 256, 0, stream>>>(nodes, method);
