@@ -94,6 +94,58 @@ def cpu_baseline(A, p, method, blocks):
                       f"4096-row blocks {list(blocks)} of {-(-r // BLOCK_ROWS)}"}
 
 
+def supernode_prec_rows(ctp, pristine, a, n, p, method, blocks, S, phase64, nelim, stream, steps=2):
+    """The same step with the Solve and the Form on the FP32 / BF16 matrix
+    cores (FP32 accumulation; pivots and D in FP64): phase times (median of
+    `steps` after one warm-up) and the difference from the FP64 step's L21
+    and first S block (the FP64 result as computed here, normwise)."""
+    import torch
+    f64 = ctp.ctp_default_opts(method)
+    w64 = ctp.workspace(n, p, f64)
+    a.copy_(pristine)
+    f = ctp.ctp_factor_supernode(a, f64, work=w64)
+    ctp.ctp_solve_supernode(a, f, f64, work=w64)
+    row0, nr = blocks[0]
+    s64 = ctp.ctp_schur(a, f, row0, nr, f64, work=w64).clone()
+    l64 = a[p:, :nelim].clone()
+    del w64
+    rows = {}
+    r = n - p
+    flops_solve = r * nelim ** 2
+    flops_form = sum((nr_ * row0_ + nr_ * (nr_ + 1) / 2.0) * 2.0 * nelim for row0_, nr_ in blocks)
+    for prec in ("fp32", "bf16"):
+        opts = ctp.ctp_default_opts(method, prec=prec)
+        work = ctp.workspace(n, p, opts)
+        times = []
+        for k in range(steps + 1):
+            E = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            a.copy_(pristine)
+            E[0].record(stream)
+            fp = ctp.ctp_factor_supernode(a, opts, work=work)
+            E[1].record(stream)
+            ctp.ctp_solve_supernode(a, fp, opts, work=work)
+            E[2].record(stream)
+            for row0_, nr_ in blocks:
+                ctp.ctp_schur(a, fp, row0_, nr_, opts, s=S[:nr_, :row0_ + nr_], work=work)
+            E[3].record(stream)
+            torch.cuda.synchronize()
+            if k:
+                times.append([E[0].elapsed_time(E[1]), E[1].elapsed_time(E[2]), E[2].elapsed_time(E[3])])
+        t = sorted(times, key=lambda x: sum(x))[len(times) // 2]
+        s_blk = ctp.ctp_schur(a, fp, row0, nr, opts, work=work)
+        dl = float((a[p:, :nelim] - l64).abs().max() / l64.abs().max().clamp(min=1.0))
+        ds = float((torch.tril(s_blk) - torch.tril(s64)).abs().max() / s64.abs().max().clamp(min=1.0))
+        rows[prec] = {"factor_ms": round(t[0], 3), "solve_ms": round(t[1], 3), "form_ms": round(t[2], 3),
+                      "solve_tflops": round(flops_solve / (t[1] * 1e-3) / 1e12, 2),
+                      "form_tflops": round(flops_form / (t[2] * 1e-3) / 1e12, 2),
+                      "rel_diff_l21_vs_fp64": dl, "rel_diff_s_block0_vs_fp64": ds}
+        del work
+    rows["fp64"] = {"factor_ms": phase64["factor"], "solve_ms": phase64["solve"], "form_ms": phase64["form"],
+                    "solve_tflops": round(flops_solve / (phase64["solve"] * 1e-3) / 1e12, 2),
+                    "form_tflops": round(flops_form / (phase64["form"] * 1e-3) / 1e12, 2)}
+    return rows
+
+
 def dense_section(N, pw=256, method="relaxed", seed=0, nrhs=8, tol=1e-14, us=(0.01, 0.5)):
     """The dense mixed-precision comparison at each threshold in us."""
     return {f"u={u}": dense_at(N, pw, method, seed, nrhs, tol, u) for u in us}
@@ -323,6 +375,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tpp", action="store_true")
+    ap.add_argument("--no-prec", action="store_true", help="skip the reduced-precision Solve/Form rows")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense mixed-precision section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-supernode section")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -453,6 +506,10 @@ def main():
         "phases_ms": phase,
         "algorithmic_gflop_per_step": round(flops / 1e9, 2),
     }
+
+    if not args.no_prec:
+        result["reduced_precision"] = supernode_prec_rows(ctp, pristine, a, n, p, args.method, blocks, S,
+                                                          phase, nelim, stream)
 
     if not args.no_tpp:
         # TPP baseline (Section 2) on the same panel, Factor+Solve: the grid-wide
