@@ -40,6 +40,14 @@ CTP_DEV double wave_max(double v) {
   return v;
 }
 
+// Orders one lane's LDS writes before the other lanes' later reads within
+// a wave (release, wave barrier, acquire at wavefront scope).
+CTP_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block of the relaxed compression

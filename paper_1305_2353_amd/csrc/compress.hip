@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void strict_rowset_kernel(int r, int p, const 
 }
 
 // Dynamic LDS: p * STRICT_CG u64 bins.
-extern __shared__ unsigned long long cmp_bins[];
+HIP_DYNAMIC_SHARED(unsigned long long, cmp_bins)
 
 CTP_DEV void strict_colmax_body(int r, int p, const double* __restrict__ a21, int lda,
                                 const int* __restrict__ J, unsigned long long* __restrict__ cbits, int ldc,
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void relaxed_topk_kernel(int r, int p, const d
 
 // One workgroup of 1024 threads.  Dynamic LDS: final candidate lists
 // (p * K Cand) + chosen rows (p ints) + a bitmap of chosen rows (r bits).
-extern __shared__ unsigned char cmp_smem[];
+HIP_DYNAMIC_SHARED(unsigned char, cmp_smem)
 
 CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, int lda, int nchunks,
                                  const Cand* __restrict__ cand, double* __restrict__ c, int ldc,
@@ -290,6 +290,7 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
           chosen[jj] = pick;
           flags[pick >> 5] |= 1u << (pick & 31);
         }
+        wave_sync();   // the flag is set before any lane tests the next column
         ++taken;
       }
       if (lane == 0) {
@@ -383,10 +384,10 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
   if (method == CTP_STRICT) {
     int* J = reinterpret_cast<int*>(base + ws.j_off);
     size_t cnt = (size_t)ldc * p;
-    fill_u64_kernel<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, stream>>>(
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)), dim3(256), 0, stream,
         reinterpret_cast<unsigned long long*>(c), cnt, 0ull);
     if (r > 0) {
-      strict_rowset_kernel<<<(r + 255) / 256, 256, 0, stream>>>(r, p, a21, lda, J, status);
+      hipLaunchKernelGGL(strict_rowset_kernel, dim3((r + 255) / 256), dim3(256), 0, stream, r, p, a21, lda, J, status);
       dim3 grid((r + STRICT_ROWS - 1) / STRICT_ROWS, (p + STRICT_CG - 1) / STRICT_CG);
       size_t lds = (size_t)p * STRICT_CG * sizeof(unsigned long long);
       if (lds > 64 * 1024) {
@@ -394,7 +395,7 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
       }
-      strict_colmax_kernel<<<grid, 256, lds, stream>>>(r, p, a21, lda, J,
+      hipLaunchKernelGGL(strict_colmax_kernel, dim3(grid), dim3(256), lds, stream, r, p, a21, lda, J,
                                                        reinterpret_cast<unsigned long long*>(c), ldc);
     }
   } else if (method == CTP_RELAXED) {
@@ -402,7 +403,7 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
     int nch = ws.relaxed_chunks;
     if (r > 0) {
       dim3 grid(p, nch);
-      relaxed_topk_kernel<<<grid, 256, 0, stream>>>(r, p, a21, lda, nch, cand, status);
+      hipLaunchKernelGGL(relaxed_topk_kernel, dim3(grid), dim3(256), 0, stream, r, p, a21, lda, nch, cand, status);
     }
     size_t lds = (size_t)p * RELAXED_TOPK * sizeof(Cand) + (size_t)p * sizeof(int) + relaxed_flag_bytes(r);
     if (r > 0 && lds > 64 * 1024) {
@@ -412,13 +413,13 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
     }
     if (r > 0) {
       int* rows = crow ? crow : reinterpret_cast<int*>(base + ws.crow_off);
-      relaxed_select_kernel<<<1, 1024, lds, stream>>>(r, p, a21, lda, nch, cand, c, ldc, rows, status);
-      relaxed_gather_kernel<<<dim3(p, (p + 255) / 256), 256, 0, stream>>>(p, a21, lda, rows, c, ldc);
+      hipLaunchKernelGGL(relaxed_select_kernel, dim3(1), dim3(1024), lds, stream, r, p, a21, lda, nch, cand, c, ldc, rows, status);
+      hipLaunchKernelGGL(relaxed_gather_kernel, dim3(p, (p + 255) / 256), dim3(256), 0, stream, p, a21, lda, rows, c, ldc);
     } else {
       size_t cnt = (size_t)ldc * p;
-      fill_u64_kernel<<<(unsigned)std::min<size_t>((cnt + 255) / 256, 4096), 256, 0, stream>>>(
+      hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)), dim3(256), 0, stream,
           reinterpret_cast<unsigned long long*>(c), cnt, 0ull);
-      if (crow) fill_i32_kernel<<<(p + 255) / 256, 256, 0, stream>>>(crow, p, -1);
+      if (crow) hipLaunchKernelGGL(fill_i32_kernel, dim3((p + 255) / 256), dim3(256), 0, stream, crow, p, -1);
     }
   } else {
     return -5;
@@ -486,20 +487,20 @@ int launch_compress_batch(int count, const BatchNode* nodes, int method, int max
                           hipStream_t stream) {
   if (count <= 0) return 0;
   if (method == CTP_STRICT) {
-    batch_zero_c_kernel<<<dim3(16, count), 256, 0, stream>>>(nodes, method);
+    hipLaunchKernelGGL(batch_zero_c_kernel, dim3(16, count), dim3(256), 0, stream, nodes, method);
     if (max_r > 0) {
-      strict_rowset_batch_kernel<<<dim3((max_r + 255) / 256, count), 256, 0, stream>>>(nodes);
+      hipLaunchKernelGGL(strict_rowset_batch_kernel, dim3((max_r + 255) / 256, count), dim3(256), 0, stream, nodes);
       const size_t lds = (size_t)max_p * STRICT_CG * sizeof(unsigned long long);
       if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)strict_colmax_batch_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
       }
-      strict_colmax_batch_kernel<<<dim3((max_r + STRICT_ROWS - 1) / STRICT_ROWS, (max_p + STRICT_CG - 1) / STRICT_CG,
-                                        count), 256, lds, stream>>>(nodes);
+      hipLaunchKernelGGL(strict_colmax_batch_kernel, dim3((max_r + STRICT_ROWS - 1) / STRICT_ROWS, (max_p + STRICT_CG - 1) / STRICT_CG,
+                                        count), dim3(256), lds, stream, nodes);
     }
   } else if (method == CTP_RELAXED) {
-    if (max_r > 0) relaxed_topk_batch_kernel<<<dim3(max_p, max_chunks, count), 256, 0, stream>>>(nodes);
+    if (max_r > 0) hipLaunchKernelGGL(relaxed_topk_batch_kernel, dim3(max_p, max_chunks, count), dim3(256), 0, stream, nodes);
     const size_t lds =
         (size_t)max_p * RELAXED_TOPK * sizeof(Cand) + (size_t)max_p * sizeof(int) + relaxed_flag_bytes(max_r);
     if (lds > 64 * 1024) {
@@ -507,7 +508,7 @@ int launch_compress_batch(int count, const BatchNode* nodes, int method, int max
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
     }
-    relaxed_select_batch_kernel<<<count, 1024, lds, stream>>>(nodes);
+    hipLaunchKernelGGL(relaxed_select_batch_kernel, dim3(count), dim3(1024), lds, stream, nodes);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;

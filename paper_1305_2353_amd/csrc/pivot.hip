@@ -155,7 +155,7 @@ struct DecideShared {
   int sk[NSLOT];
 };
 
-extern __shared__ double pv_dyn[];
+HIP_DYNAMIC_SHARED(double, pv_dyn)
 __shared__ DecideShared pv_sh;
 __shared__ double pv_d[2 * CTP_MAX_P];
 __shared__ int pv_perm[CTP_MAX_P];
@@ -1044,7 +1044,7 @@ int launch_batch_setup(int count, const ctp_node* in, int method, unsigned flags
   PivotArgs* pargs = reinterpret_cast<PivotArgs*>(base + align_up((size_t)count * sizeof(BatchNode), 256));
   unsigned int* counter = reinterpret_cast<unsigned int*>(
       base + align_up((size_t)count * sizeof(BatchNode), 256) + align_up((size_t)count * sizeof(PivotArgs), 256));
-  batch_setup_kernel<<<(count + 127) / 128, 128, 0, stream>>>(in, count, method, flags, u, small, panels, s, perm,
+  hipLaunchKernelGGL(batch_setup_kernel, dim3((count + 127) / 128), dim3(128), 0, stream, in, count, method, flags, u, small, panels, s, perm,
                                                              piv, d, nelim, status, base, nodes, pargs, reset);
   *nodes_out = nodes;
   *pargs_out = pargs;
@@ -1062,17 +1062,17 @@ int launch_pivot_batch(int count, const void* pargs, int max_p, int max_r, hipSt
     case 256:
       e0 = pivot_lds_attr(pivot_factor_batch_kernel<256>, lds);
       if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
-      pivot_factor_batch_kernel<256><<<count, 256, lds, stream>>>(a, count);
+      hipLaunchKernelGGL(pivot_factor_batch_kernel<256>, dim3(count), dim3(256), lds, stream, a, count);
       break;
     case 512:
       e0 = pivot_lds_attr(pivot_factor_batch_kernel<512>, lds);
       if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
-      pivot_factor_batch_kernel<512><<<count, 512, lds, stream>>>(a, count);
+      hipLaunchKernelGGL(pivot_factor_batch_kernel<512>, dim3(count), dim3(512), lds, stream, a, count);
       break;
     default:
       e0 = pivot_lds_attr(pivot_factor_batch_kernel<1024>, lds);
       if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
-      pivot_factor_batch_kernel<1024><<<count, 1024, lds, stream>>>(a, count);
+      hipLaunchKernelGGL(pivot_factor_batch_kernel<1024>, dim3(count), dim3(1024), lds, stream, a, count);
       break;
   }
   hipError_t e = hipGetLastError();
@@ -1101,13 +1101,13 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
   if (one_wg) {
     if (nt == 256) {
       e0 = pivot_lds_attr(pivot_factor_wg_kernel<256>, lds);
-      if (e0 == hipSuccess) pivot_factor_wg_kernel<256><<<1, 256, lds, stream>>>(g);
+      if (e0 == hipSuccess) hipLaunchKernelGGL(pivot_factor_wg_kernel<256>, dim3(1), dim3(256), lds, stream, g);
     } else if (nt == 512) {
       e0 = pivot_lds_attr(pivot_factor_wg_kernel<512>, lds);
-      if (e0 == hipSuccess) pivot_factor_wg_kernel<512><<<1, 512, lds, stream>>>(g);
+      if (e0 == hipSuccess) hipLaunchKernelGGL(pivot_factor_wg_kernel<512>, dim3(1), dim3(512), lds, stream, g);
     } else {
       e0 = pivot_lds_attr(pivot_factor_wg_kernel<1024>, lds);
-      if (e0 == hipSuccess) pivot_factor_wg_kernel<1024><<<1, 1024, lds, stream>>>(g);
+      if (e0 == hipSuccess) hipLaunchKernelGGL(pivot_factor_wg_kernel<1024>, dim3(1), dim3(1024), lds, stream, g);
     }
     if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
     hipError_t e = hipGetLastError();
@@ -1118,16 +1118,16 @@ int launch_pivot_factor(int p, double* a11, int lda, int r, double* R, int ldr, 
   if (e0 != hipSuccess) return CTP_ERR_HIP_BASE - (int)e0;
   const size_t sq = (size_t)p * p;
   const unsigned init_blocks = (unsigned)std::min<size_t>((sq + 255) / 256 + 1, 2048);
-  pivot_init_kernel<<<init_blocks, 256, 0, stream>>>(g);
+  hipLaunchKernelGGL(pivot_init_kernel, dim3(init_blocks), dim3(256), 0, stream, g);
   const int tw = (p + APPLY_TILE - 1) / APPLY_TILE;
   const int apply_blocks = tw * tw + ((r + APPLY_TILE - 1) / APPLY_TILE) * tw;
   // every full batch holds at least NSLOT-1 eliminated columns
   const int rounds = p / (NSLOT - 1) + 2;
   for (int q = 0; q < rounds; ++q) {
-    if (nt == 256) pivot_decide_kernel<256><<<1, 256, lds, stream>>>(g);
-    else if (nt == 512) pivot_decide_kernel<512><<<1, 512, lds, stream>>>(g);
-    else pivot_decide_kernel<1024><<<1, 1024, lds, stream>>>(g);
-    if (apply_blocks > 0) pivot_apply_kernel<<<apply_blocks, 256, 0, stream>>>(g);
+    if (nt == 256) hipLaunchKernelGGL(pivot_decide_kernel<256>, dim3(1), dim3(256), lds, stream, g);
+    else if (nt == 512) hipLaunchKernelGGL(pivot_decide_kernel<512>, dim3(1), dim3(512), lds, stream, g);
+    else hipLaunchKernelGGL(pivot_decide_kernel<1024>, dim3(1), dim3(1024), lds, stream, g);
+    if (apply_blocks > 0) hipLaunchKernelGGL(pivot_apply_kernel, dim3(apply_blocks), dim3(256), 0, stream, g);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;

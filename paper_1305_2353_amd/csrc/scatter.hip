@@ -106,7 +106,7 @@ int launch_extend_add(int n, int p, const double* a, int lda, const double* s, i
                       int ld22, int* status, hipStream_t stream) {
   if (n <= 0) return 0;
   const ScatterArgs g{n, p, lda, lds, np, pp, ldf, ld22, a, s, perm, nelim, map, f, f22};
-  extend_add_kernel<<<(unsigned)ea_tiles(n), 256, 0, stream>>>(g, status);
+  hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)ea_tiles(n)), dim3(256), 0, stream, g, status);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
@@ -140,7 +140,7 @@ int launch_extend_add_batch(int count, const ctp_scatter_task* tasks, long long 
                             const double* s, const int* perm, const int* nelim, const int* map, double* fpanels,
                             double* f22, int* status, hipStream_t stream) {
   if (count <= 0 || tiles <= 0) return 0;
-  extend_add_batch_kernel<<<(unsigned)tiles, 256, 0, stream>>>(tasks, count, panels, s, perm, nelim, map, fpanels,
+  hipLaunchKernelGGL(extend_add_batch_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, tasks, count, panels, s, perm, nelim, map, fpanels,
                                                                f22, status);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;

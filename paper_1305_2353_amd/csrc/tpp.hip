@@ -477,6 +477,7 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
     if (S.nelim >= p) break;
     if (S.m >= p) {
       if (S.progress) {
+        __syncthreads();   // every thread has read m and progress before they change
         if (threadIdx.x == 0) {
           S.progress = 0;
           S.m = S.nelim;
@@ -614,37 +615,41 @@ __global__ __launch_bounds__(TPP_THREADS) void tpp_step_kernel(TppArgs g) {
   double l[TPP_NSLOT];
   double* row = g.xr + (rrow ? i : 0);
   const int ldr = g.ldr;
+  // 1. multipliers of the new slot(s): every wave computes them (the same
+  //    bits) from the eliminated columns' entries, wave 0 stores them there
+  //    once every wave has read those entries
+  double lv1 = 0.0, lv2 = 0.0;
   if (rrow) {
     // multipliers of the slots materialised in earlier steps
     const int nold = S.mat_n ? S.mat_s0 : ns;
 #pragma unroll
     for (int s = 0; s < TPP_NSLOT; ++s) l[s] = s < nold ? row[(size_t)S.slot_var[s] * ldr] : 0.0;
-    // 1. multipliers of the new slot(s): every wave computes them (the same
-    //    bits), wave 0 stores them
     if (S.mat_n == 1) {
       const int s0 = S.mat_s0, v = S.slot_var[s0];
       const double x = tpp_lazy(row[(size_t)v * ldr], l, S, g.w, p, v, s0);
-      const double lv = x / S.slot_x[s0][0];
-      if (wave == 0) row[(size_t)v * ldr] = lv;
+      lv1 = x / S.slot_x[s0][0];
 #pragma unroll
       for (int s = 0; s < TPP_NSLOT; ++s)
-        if (s == s0) l[s] = lv;
+        if (s == s0) l[s] = lv1;
     } else if (S.mat_n == 2) {
       const int s0 = S.mat_s0, v1 = S.slot_var[s0], v2 = S.slot_var[s0 + 1];
       const double x1 = tpp_lazy(row[(size_t)v1 * ldr], l, S, g.w, p, v1, s0);
       const double x2 = tpp_lazy(row[(size_t)v2 * ldr], l, S, g.w, p, v2, s0);
       const double i11 = S.slot_x[s0][0], i21 = S.slot_x[s0][1], i22 = S.slot_x[s0 + 1][1];
-      const double l1 = x1 * i11 + x2 * i21;
-      const double l2 = x1 * i21 + x2 * i22;
-      if (wave == 0) {
-        row[(size_t)v1 * ldr] = l1;
-        row[(size_t)v2 * ldr] = l2;
-      }
+      lv1 = x1 * i11 + x2 * i21;
+      lv2 = x1 * i21 + x2 * i22;
 #pragma unroll
       for (int s = 0; s < TPP_NSLOT; ++s) {
-        if (s == s0) l[s] = l1;
-        if (s == s0 + 1) l[s] = l2;
+        if (s == s0) l[s] = lv1;
+        if (s == s0 + 1) l[s] = lv2;
       }
+    }
+  }
+  if (S.mat_n) __syncthreads();
+  if (rrow) {
+    if (wave == 0 && S.mat_n) {
+      row[(size_t)S.slot_var[S.mat_s0] * ldr] = lv1;
+      if (S.mat_n == 2) row[(size_t)S.slot_var[S.mat_s0 + 1] * ldr] = lv2;
     }
     // 2. a zero pivot's column
     if (S.zero_var >= 0 && wave == 0) row[(size_t)S.zero_var * ldr] = 0.0;
@@ -751,15 +756,15 @@ int launch_tpp_grid(int n, int p, double* a, int lda, int root, double u, double
   g.st = static_cast<TppState*>(state);
   const size_t work = (size_t)p * p + (size_t)g.r * p;
   const unsigned blocks = (unsigned)std::min<size_t>((work + 255) / 256 + 1, 4096);
-  tpp_init_kernel<<<blocks, 256, 0, stream>>>(g);
-  tpp_start_kernel<<<1, TPP_THREADS, 0, stream>>>(g);
+  hipLaunchKernelGGL(tpp_init_kernel, dim3(blocks), dim3(256), 0, stream, g);
+  hipLaunchKernelGGL(tpp_start_kernel, dim3(1), dim3(TPP_THREADS), 0, stream, g);
   // a pass tests every remaining column once; a pass without progress ends
   // the loop or (root) makes a fallback step: at most (p + 1) passes
   const long long max_steps = (long long)(p + 2) * (p + 2) + 16;
   long long steps = 0;
   int chunk = p + 32;
   for (;;) {
-    for (int q = 0; q < chunk; ++q) tpp_step_kernel<<<g.groups, TPP_THREADS, 0, stream>>>(g);
+    for (int q = 0; q < chunk; ++q) hipLaunchKernelGGL(tpp_step_kernel, dim3(g.groups), dim3(TPP_THREADS), 0, stream, g);
     steps += chunk;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
@@ -771,7 +776,7 @@ int launch_tpp_grid(int n, int p, double* a, int lda, int root, double u, double
     if (steps > max_steps) return CTP_ERR_HIP_BASE - (int)hipErrorUnknown;
     chunk = 64;
   }
-  tpp_finish_kernel<<<blocks, 256, 0, stream>>>(g);
+  hipLaunchKernelGGL(tpp_finish_kernel, dim3(blocks), dim3(256), 0, stream, g);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
 }
