@@ -47,6 +47,13 @@ FORM_COUNTERS = {
 }
 
 
+def _finite_or_none(v):
+    """A backward error for the JSON line: None where refinement met a NaN or
+    an overflow (the library reports those as infinite)."""
+    import math
+    return v if math.isfinite(v) else None
+
+
 def form_traffic(n, p):
     import hashlib
     src = os.path.join(ROOT, "paper_1305_2353_amd", "csrc", "schur.hip")
@@ -188,7 +195,8 @@ def dense_at(N, pw=256, method="relaxed", seed=0, nrhs=8, tol=1e-14, u=0.5):
             t2 = time.perf_counter()
             cur = {"factor_ms": round((t1 - t0) * 1e3, 2), "refine_ms": round((t2 - t1) * 1e3, 2),
                    "total_ms": round((t2 - t0) * 1e3, 2), "refine_steps": steps,
-                   "bwd_err": hist[-1], "bwd_hist": [float("%.3g" % h) for h in hist],
+                   "bwd_err": _finite_or_none(hist[-1]),
+                   "bwd_hist": [_finite_or_none(float("%.3g" % h)) for h in hist],
                    "reached": bool(hist[-1] <= tol), "panels": f["npanels"],
                    "status": int(f["status"].item())}
             if best is None or cur["total_ms"] < best["total_ms"]:

@@ -440,7 +440,10 @@ int ctp_ldlt_solve(int N, int nrhs, const double* a, int lda, const int* perm, c
  * (lda0), f / ldf: the factor array of ctp_ldlt_dense; x (N x nrhs, ldx)
  * output.  steps (host, may be NULL): corrections applied; bwd_hist (host,
  * may be NULL, max_steps + 1 entries): backward error before each
- * correction and after the last.  Synchronizes once per step. */
+ * correction and after the last.  A NaN or an overflow in the residual or
+ * the iterate gives an infinite backward error, which ends the refinement
+ * (reported as such in bwd_hist, not converged).  Synchronizes once per
+ * step. */
 int ctp_ldlt_refine(int N, int nrhs, const double* a0, int lda0, const double* f, int ldf,
                     const int* perm, const int* piv, const double* d, const double* b, int ldb,
                     double* x, int ldx, const ctp_opts* opts, int pw, double tol, int max_steps,

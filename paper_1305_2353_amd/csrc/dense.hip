@@ -448,12 +448,14 @@ __global__ __launch_bounds__(256) void dense_norms_kernel(const double* __restri
   double va = 0.0;
   double vr[SW_MAXRHS], vx[SW_MAXRHS], vb[SW_MAXRHS];
   for (int c = 0; c < SW_MAXRHS; ++c) vr[c] = vx[c] = vb[c] = 0.0;
+  // a NaN counts as infinite (fmax would drop it from the maxima)
+  auto mag = [](double v) { return v != v ? INFINITY : fabs(v); };
   if (i < N) {
-    va = arow[i];
+    va = mag(arow[i]);
     for (int c = 0; c < nrhs; ++c) {
-      vr[c] = fabs(r[(size_t)c * ldr + i]);
-      vx[c] = fabs(x[(size_t)c * ldx + i]);
-      vb[c] = fabs(b[(size_t)c * ldb + i]);
+      vr[c] = mag(r[(size_t)c * ldr + i]);
+      vx[c] = mag(x[(size_t)c * ldx + i]);
+      vb[c] = mag(b[(size_t)c * ldb + i]);
     }
   }
   va = wave_max(va);
@@ -806,14 +808,19 @@ int ctp_ldlt_refine(int N, int nrhs, const double* a0, int lda0, const double* f
     if (hipMemcpyAsync(hn.data(), norms, nn * sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
       return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+    // an infinite norm (overflow, or a NaN in A, b, x or r) gives an
+    // infinite backward error, which ends the refinement unconverged
     double be = 0.0;
     for (int c = 0; c < nrhs; ++c) {
-      const double den = hn[0] * hn[1 + nrhs + c] + hn[1 + 2 * nrhs + c];
-      const double v = den > 0.0 ? hn[1 + c] / den : 0.0;
+      const double nr = hn[1 + c], den = hn[0] * hn[1 + nrhs + c] + hn[1 + 2 * nrhs + c];
+      double v;
+      if (!std::isfinite(nr) || !std::isfinite(den)) v = INFINITY;
+      else if (den > 0.0) v = nr / den;
+      else v = nr > 0.0 ? INFINITY : 0.0;
       be = v > be ? v : be;
     }
     if (bwd_hist) bwd_hist[k] = be;
-    if (be <= tol || k >= max_steps) break;
+    if (be <= tol || k >= max_steps || !std::isfinite(be)) break;
     rc = ctp_ldlt_solve(N, nrhs, f, ldf, perm, piv, d, r, N, opts, pw, work, lwork, stream);
     if (rc) return rc;
     dense_axpy_kernel<<<eg, 256, 0, stream>>>(x, ldx, r, N, N, nrhs);

@@ -105,6 +105,23 @@ def test_dense_solve_and_fp64_refinement(N, pw):
     assert hist[-1] < 1e-15 or steps == 3
 
 
+def test_refinement_stops_on_nan():
+    """A NaN in the right-hand side reaches the residual: the backward error
+    is infinite and refinement stops there, not converged (a NaN must not
+    read as a zero error)."""
+    from paper_1305_2353_amd import ctp
+    N, pw = 300, 64
+    A, lam, B = dense_indefinite(N, seed=5, lam_lo=1e-2, nrhs=2)
+    _announce("dense refine nan", N, pw)
+    a, f, opts, work = _gpu_dense(A, pw, "relaxed")
+    B = B.copy()
+    B[7, 1] = np.nan
+    b = ctp.device_panel(B)
+    X, steps, hist = ctp.ctp_ldlt_refine(ctp.device_panel(A), a, f, b, opts, work, tol=1e-14, max_steps=5)
+    assert steps == 0
+    assert len(hist) == 1 and np.isinf(hist[0])
+
+
 def test_dense_solve_with_two_by_two_pivots_across_blocks():
     """Indefinite input with tiny diagonals: many 2x2 pivots, some of which
     straddle the 128-column blocks of the solve."""
