@@ -418,8 +418,13 @@ int ctp_dense_workspace_size(int N, int pw, const ctp_opts* opts, int nrhs_max, 
  * int, OR of the panels' CTP_STATUS_* bits.  npanels: host int (may be
  * NULL), number of panels.  work: ctp_dense_workspace_size bytes; it also
  * keeps the inverses of L's diagonal blocks for ctp_ldlt_solve, so pass the
- * same workspace, unchanged, to the solve.  The call synchronizes the
- * stream once per panel (panel widths depend on the delays).  Errors:
+ * same workspace, unchanged, to the solve.  The factorization runs on two
+ * streams of the library's own (one pair per device, created on first use):
+ * the chain of panels, and the trailing updates beyond the next panel, which
+ * overlap the next panel's factorization (look-ahead).  They start after
+ * the work already on `stream` and
+ * `stream` waits for them; the call synchronizes the chain once per panel
+ * (panel widths depend on the delays).  Errors:
  * -1..-12 argument k, CTP_ERR_PANEL_TOO_WIDE when delays pile up past
  * CTP_MAX_P, supernode errors passed through. */
 int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,

@@ -19,8 +19,10 @@
 //   chunk), the top RELAXED_TOPK (|a|, row) pairs in the total order
 //   "larger value first, lower row first"; pass 2 (one workgroup) merges
 //   them per column, walks the columns in order taking the first unflagged
-//   candidate, rescans a column in full in the rare case that all its
-//   candidates are taken, and gathers the chosen signed rows into C.
+//   candidate, rescans a column in full when all its candidates are taken
+//   (rare on random panels; common on Schur complements dominated by a
+//   low-rank term, whose columns all rank the rows alike), and gathers the
+//   chosen signed rows into C.
 
 #include "common.h"
 
@@ -303,13 +305,28 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
     j = s_pick;
     if (!s_need_scan) break;
     // Full rescan of column j over the rows not yet chosen.
+    // eight loads in flight per thread, the chosen rows masked afterwards
+    // (the comparisons are a total order, so the result does not depend on
+    // the order in which rows are visited)
     const double* colp = a21 + (size_t)j * lda;
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < r; i += blockDim.x) {
-      if ((flags[i >> 5] >> (i & 31)) & 1u) continue;
-      const double v = fabs(colp[i]);
-      if (better(v, i, bv, bi)) { bv = v; bi = i; }
+    constexpr int RU = 8;
+    for (int i0 = threadIdx.x; i0 < r; i0 += RU * (int)blockDim.x) {
+      double v[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        v[u] = i < r ? colp[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        if (i < r && !((flags[i >> 5] >> (i & 31)) & 1u) && better(fabs(v[u]), i, bv, bi)) {
+          bv = fabs(v[u]);
+          bi = i;
+        }
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       const double ov = __shfl_xor(bv, off, 64);
@@ -318,12 +335,16 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
     }
     if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
     __syncthreads();
+    // every thread merges the waves' results (the same pick everywhere);
+    // thread 0 records it, and wave 0, which walks next, is ordered after
+    // that by a wave sync (the other waves read the flags again only after
+    // the walk's barrier)
+    double xv = red_v[0];
+    int xi = red_i[0];
+    for (int w = 1; w < nwaves; ++w)
+      if (better(red_v[w], red_i[w], xv, xi)) { xv = red_v[w]; xi = red_i[w]; }
+    const int pick = (xv >= 0.0) ? xi : -1;
     if (threadIdx.x == 0) {
-      double xv = red_v[0];
-      int xi = red_i[0];
-      for (int w = 1; w < nwaves; ++w)
-        if (better(red_v[w], red_i[w], xv, xi)) { xv = red_v[w]; xi = red_i[w]; }
-      const int pick = (xv >= 0.0) ? xi : -1;
       chosen[j] = pick;
       if (pick >= 0) {
         flags[pick >> 5] |= 1u << (pick & 31);
@@ -331,7 +352,7 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
       }
       atomicOr(status, ST_RELAXED_RESCAN);
     }
-    __syncthreads();
+    wave_sync();
     ++j;
   }
   __syncthreads();

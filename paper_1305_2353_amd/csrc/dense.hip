@@ -34,7 +34,9 @@
 // (one launch per block, every workgroup recomputing the small product on
 // the matrix cores).
 
+#include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -42,9 +44,9 @@
 namespace ctp {
 
 int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, int ldw,
-                       const int* nelim, double* c, int ldc, hipStream_t stream);
-int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops,
-                           hipStream_t stream);
+                       const int* nelim, double* c, int ldc, int tc0, int tc1, hipStream_t stream);
+int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops, int tc0,
+                           int tc1, hipStream_t stream);
 
 constexpr int DB = 128;   // diagonal block of the solve
 
@@ -527,8 +529,11 @@ __global__ __launch_bounds__(256) void dense_sym_outer_kernel(const double* __re
 // ---------------------------------------------------------------------------
 
 struct DenseWork {
-  size_t sn_off = 0, sn_bytes = 0;     // supernode workspace (largest panel)
-  size_t pperm_off = 0, ppiv_off = 0, pd_off = 0, pnelim_off = 0, pstatus_off = 0;
+  size_t sn_off = 0, sn_bytes = 0;     // two supernode workspaces (largest panel), sn_bytes each
+  // panel outputs, two sets (stride pout_bytes): panels alternate between
+  // the two so that a panel's trailing update can still read its W and
+  // nelim while the next panel is factored
+  size_t pperm_off = 0, ppiv_off = 0, pd_off = 0, pnelim_off = 0, pstatus_off = 0, pout_bytes = 0;
   size_t linv_off = 0, linvt_off = 0;  // inverses of the diagonal blocks
   size_t w32_off = 0;                  // FP32 trailing matrix (reduced precision)
   int ld32 = 0;
@@ -550,13 +555,16 @@ static DenseWork dense_layout(int N, int pw, const ctp_opts* o, int nrhs_max) {
   // buffer ((n - p) x p): the size at (2N, pmax) bounds every panel shape
   ctp_workspace_size(2 * N, pmax, &so, &sn);
   w.sn_off = off;
-  w.sn_bytes = sn;
-  off = align_up(off + sn, 256);
+  w.sn_bytes = align_up(sn, 256);
+  off = align_up(off + 2 * w.sn_bytes, 256);
+  const size_t p0 = off;
   w.pperm_off = off; off = align_up(off + CTP_MAX_P * sizeof(int), 256);
   w.ppiv_off = off; off = align_up(off + CTP_MAX_P * sizeof(int), 256);
   w.pd_off = off; off = align_up(off + 2 * CTP_MAX_P * sizeof(double), 256);
   w.pnelim_off = off; off = align_up(off + sizeof(int), 256);
   w.pstatus_off = off; off = align_up(off + sizeof(int), 256);
+  w.pout_bytes = off - p0;
+  off += w.pout_bytes;
   const size_t nbk = (size_t)dense_nblocks(N);
   w.linv_off = off; off = align_up(off + nbk * DB * DB * sizeof(double), 256);
   w.linvt_off = off; off = align_up(off + nbk * DB * DB * sizeof(double), 256);
@@ -641,8 +649,38 @@ int ctp_dense_workspace_size(int N, int pw, const ctp_opts* opts, int nrhs_max, 
   return 0;
 }
 
+// The dense driver's two streams, one pair per device, created on first use
+// (default priority, non-blocking): 0 the factorization chain, 1 the
+// trailing updates that overlap it.  (Restricting stream 1 to all CUs but a
+// few, so that the chain's one-workgroup pivot search always finds a free
+// CU, measured 6 ms slower per factorization at N = 16384.)
+static hipStream_t dense_stream(int which) {
+  static hipStream_t st[64][2] = {};
+  static std::mutex m;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(m);
+  hipStream_t& s = st[dev][which];
+  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  return s;
+}
+
+// Right-looking factorization of the dense matrix as a chain of supernodes
+// (panel = the previous panel's delayed columns + the next pw columns; the
+// last panel with CTP_FLAG_ROOT), with a look-ahead of one panel: the
+// trailing update of panel k is split at the new columns of panel k+1.
+// Those tile columns are updated in the chain right away, so panel k+1 can
+// be factored at once; the rest of the update runs on the second stream,
+// beside panel k+1's compression, pivot search and solve (which touch only
+// panel k+1's own columns).  Panels alternate between two supernode
+// workspaces and two sets of panel outputs, because the rest of panel k's
+// update still reads its W and nelim while panel k+1 is factored.  Before
+// panel k+1's own updates, and before its row interchanges are applied to
+// the columns left of it (which include the L21 rows that the rest of panel
+// k's update reads), the chain waits for that rest.  The caller's stream is
+// joined by events at the start and at the end.
 int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
-                   double* d, int* status, int* npanels, void* work, size_t lwork, hipStream_t stream) {
+                   double* d, int* status, int* npanels, void* work, size_t lwork, hipStream_t caller) {
   int rc = dense_check(N, pw, a, lda, opts);
   if (rc) return rc;
   if (N > 0 && (!perm || !piv || !d)) return -6;
@@ -651,14 +689,33 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
   if (!work || lwork < L.total) return -12;
   if (N == 0) return 0;
   unsigned char* base = static_cast<unsigned char*>(work);
-  void* sn = base + L.sn_off;
-  int* pperm = reinterpret_cast<int*>(base + L.pperm_off);
-  int* ppiv = reinterpret_cast<int*>(base + L.ppiv_off);
-  double* pd = reinterpret_cast<double*>(base + L.pd_off);
-  int* pnelim = reinterpret_cast<int*>(base + L.pnelim_off);
-  int* pstatus = reinterpret_cast<int*>(base + L.pstatus_off);
   float* w32 = reinterpret_cast<float*>(base + L.w32_off);
   const bool lowp = opts->prec != 0;
+  hipStream_t stream = dense_stream(0), side = dense_stream(1);
+  if (!stream || !side) return CTP_ERR_HIP_BASE - (int)hipErrorInvalidValue;
+  hipEvent_t ev_ready = nullptr, ev_rest = nullptr;
+  if (hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_rest, hipEventDisableTiming) != hipSuccess) {
+    if (ev_ready) hipEventDestroy(ev_ready);
+    return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+  }
+  // the chain starts after the caller's earlier work
+  if (hipEventRecord(ev_ready, caller) != hipSuccess || hipStreamWaitEvent(stream, ev_ready, 0) != hipSuccess) {
+    hipEventDestroy(ev_ready);
+    hipEventDestroy(ev_rest);
+    return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+  }
+  bool rest_pending = false;
+  // every exit: the chain takes over the side stream's last work, the
+  // caller's stream takes over the chain
+  auto finish = [&](int code) {
+    if (rest_pending) hipStreamWaitEvent(stream, ev_rest, 0);
+    hipEventRecord(ev_ready, stream);
+    hipStreamWaitEvent(caller, ev_ready, 0);
+    hipEventDestroy(ev_ready);
+    hipEventDestroy(ev_rest);
+    return code;
+  };
 
   dense_iota_kernel<<<(N + 255) / 256, 256, 0, stream>>>(perm, N, N);
   if (lowp) dense_to_f32_kernel<<<dim3(4, N), 256, 0, stream>>>(a, lda, w32, L.ld32, N);
@@ -667,44 +724,79 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
   int k0 = 0, width = pw < N ? pw : N, carried = 0, panels = 0;
   int acc_status = 0;
   while (k0 < N) {
-    if (width > CTP_MAX_P) return -900;   // delays grew a panel past CTP_MAX_P
+    if (width > CTP_MAX_P) return finish(-900);   // delays grew a panel past CTP_MAX_P
     const int n = N - k0;
     const bool root = n == width;
     double* ap = a + (size_t)k0 * lda + k0;
+    const int q = panels & 1;
+    unsigned char* sn = base + L.sn_off + q * L.sn_bytes;
+    const size_t po_off = q * L.pout_bytes;
+    int* pperm = reinterpret_cast<int*>(base + L.pperm_off + po_off);
+    int* ppiv = reinterpret_cast<int*>(base + L.ppiv_off + po_off);
+    double* pd = reinterpret_cast<double*>(base + L.pd_off + po_off);
+    int* pnelim = reinterpret_cast<int*>(base + L.pnelim_off + po_off);
+    int* pstatus = reinterpret_cast<int*>(base + L.pstatus_off + po_off);
     // reduced precision: the new columns of the panel come from the FP32 copy
     if (lowp && width > carried)
       dense_from_f32_kernel<<<dim3(4, width - carried), 256, 0, stream>>>(a, lda, w32, L.ld32, k0 + carried, N);
     po.flags = opts->flags | (root ? CTP_FLAG_ROOT : 0u);
     rc = ctp_supernode(n, width, ap, lda, &po, pperm, ppiv, pd, pnelim, pstatus, nullptr, 0, sn, L.sn_bytes, stream);
-    if (rc) return rc;
-    if (k0 > 0) dense_perm_left_kernel<<<k0, 256, 0, stream>>>(a, lda, k0, width, pperm);
-    dense_bookkeep_kernel<<<1, 512, 0, stream>>>(k0, width, pperm, ppiv, pd, pnelim, perm, piv, d);
+    if (rc) return finish(rc);
     int ne = 0, st = 0;
     if (hipMemcpyAsync(&ne, pnelim, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipMemcpyAsync(&st, pstatus, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipStreamSynchronize(stream) != hipSuccess)
-      return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+      return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
     acc_status |= st;
     ++panels;
+    // the previous panel's remaining update is done before this panel's
+    // interchanges reach the columns left of it and before its own updates
+    if (rest_pending) {
+      if (hipStreamWaitEvent(stream, ev_rest, 0) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+      rest_pending = false;
+    }
+    if (k0 > 0) dense_perm_left_kernel<<<k0, 256, 0, stream>>>(a, lda, k0, width, pperm);
+    dense_bookkeep_kernel<<<1, 512, 0, stream>>>(k0, width, pperm, ppiv, pd, pnelim, perm, piv, d);
+    const int next_carried = width - ne, next_k0 = k0 + ne;
+    const int next_width = N - next_k0 < next_carried + pw ? N - next_k0 : next_carried + pw;
     if (n > width && ne > 0) {
       // the W = L21 D that the solve left in the supernode workspace
       Workspace ws = workspace_layout(n, width, po.method);
-      const double* w = reinterpret_cast<const double*>(static_cast<unsigned char*>(sn) + ws.w_off);
-      if (!lowp) {
-        rc = launch_schur_w_sub(n, width, ap, lda, w, ws.ldw, pnelim,
-                                a + (size_t)(k0 + width) * lda + (k0 + width), lda, stream);
-      } else {
-        // the operand rows of L21 and W that the reduced-precision Solve
-        // converted into the supernode workspace
-        rc = launch_lowp_update_ops(n - width, width, pnelim, w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width),
-                                    L.ld32, opts->prec, static_cast<unsigned char*>(sn) + align_up(ws.total, 256),
-                                    stream);
+      const double* w = reinterpret_cast<const double*>(sn + ws.w_off);
+      const int r = n - width;
+      const int nt = (r + 127) / 128;
+      // tile columns holding the next panel's new columns
+      const int tc = std::min(nt, (next_width - next_carried + 127) / 128);
+      if (tc < nt && hipEventRecord(ev_ready, stream) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+      for (int part = 0; part < 2; ++part) {
+        const int t0 = part == 0 ? 0 : tc, t1 = part == 0 ? tc : nt;
+        if (t0 >= t1) continue;
+        hipStream_t s = part == 0 ? stream : side;
+        if (part == 1 && hipStreamWaitEvent(side, ev_ready, 0) != hipSuccess)
+          return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+        if (!lowp) {
+          rc = launch_schur_w_sub(n, width, ap, lda, w, ws.ldw, pnelim,
+                                  a + (size_t)(k0 + width) * lda + (k0 + width), lda, t0, t1, s);
+        } else {
+          // the operand rows of L21 and W that the reduced-precision Solve
+          // converted into the supernode workspace
+          rc = launch_lowp_update_ops(r, width, pnelim, w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width),
+                                      L.ld32, opts->prec, sn + align_up(ws.total, 256), t0, t1, s);
+        }
+        if (rc) return finish(rc);
+        if (part == 1) {
+          if (hipEventRecord(ev_rest, side) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+          rest_pending = true;
+        }
       }
-      if (rc) return rc;
     }
-    carried = width - ne;
-    k0 += ne;
-    width = N - k0 < carried + pw ? N - k0 : carried + pw;
+    carried = next_carried;
+    k0 = next_k0;
+    width = next_width;
+  }
+  if (rest_pending) {
+    hipStreamWaitEvent(stream, ev_rest, 0);
+    rest_pending = false;
   }
   // solve preparation
   {
@@ -718,10 +810,10 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
   }
   int* st_out = status;
   hipMemcpyAsync(st_out, &acc_status, sizeof(int), hipMemcpyHostToDevice, stream);
-  if (hipStreamSynchronize(stream) != hipSuccess) return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+  if (hipStreamSynchronize(stream) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
   if (npanels) *npanels = panels;
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e;
+  return finish(e == hipSuccess ? 0 : CTP_ERR_HIP_BASE - (int)e);
 }
 
 int ctp_ldlt_solve(int N, int nrhs, const double* a, int lda, const int* perm, const int* piv,

@@ -84,6 +84,7 @@ struct LowpArgs {
   int lds, tiled, row0, nrows;
   int ntm, ntn;      // tiles down and across
   int per_xcd;
+  int tn0;           // first tile column (trailing update over a range of tile columns)
 };
 
 // FORM = false: the dense trailing update; true: the supernode Form.
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(LP_THREADS, 2) void lowp_update_kernel(LowpArgs g) 
   const int in_grp = tile % per_group;
   const int gm = min(LP_GROUP, g.ntm - grp * LP_GROUP);
   const int tm = grp * LP_GROUP + in_grp % gm;
-  const int tn = in_grp / gm;
+  const int tn = in_grp / gm + g.tn0;
   const int i0 = g.row0 + tm * LP_BM, j0 = tn * LP_BM;
   if (j0 > i0 + LP_BM - 1) return;   // strictly above the diagonal
   const int iend = FORM ? g.row0 + g.nrows : g.r;   // rows of this call
@@ -248,14 +249,22 @@ static LowpArgs lowp_args(int r, int K, const int* nelim, void* ops) {
 }
 
 // The trailing update from operand rows already converted (by
-// launch_lowp_convert with the same r and K).
-int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops,
-                           hipStream_t stream) {
+// launch_lowp_convert with the same r and K), on the 128-wide tile columns
+// [tc0, tc1) of C (rows from the first of them down); tc1 < 0: to the last.
+int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops, int tc0,
+                           int tc1, hipStream_t stream) {
   if (r <= 0 || K <= 0) return 0;
+  const int nt = (r + LP_BM - 1) / LP_BM;
+  if (tc1 < 0 || tc1 > nt) tc1 = nt;
+  if (tc0 < 0) tc0 = 0;
+  if (tc0 >= tc1) return 0;
   LowpArgs g = lowp_args(r, K, nelim, ops);
   g.c = c;
   g.ldc = ldc;
-  g.ntm = g.ntn = (r + LP_BM - 1) / LP_BM;
+  g.row0 = tc0 * LP_BM;   // rows above the first tile column's diagonal are not touched
+  g.tn0 = tc0;
+  g.ntm = (r - g.row0 + LP_BM - 1) / LP_BM;
+  g.ntn = tc1 - tc0;
   const int total = g.ntm * g.ntn;
   g.per_xcd = (total + LP_NXCD - 1) / LP_NXCD;
   const unsigned grid = g.per_xcd * LP_NXCD;

@@ -213,6 +213,7 @@ struct SchurWArgs {
   int ntm, ntn;
   int per_xcd;
   int tiled;           // 1: s is this tile's own 128 x 128 block (ld 128)
+  int tn0 = 0;         // first tile column (a range of tile columns)
 };
 
 // Main loop and epilogue of one tile.  VEC: every row of both operands
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(SC_THREADS, 2) void schur_w_kernel(SchurWArgs g) {
   const int in_grp = tile % per_group;
   const int gm = min(SC_GROUP, g.ntm - grp * SC_GROUP);
   const int tm = grp * SC_GROUP + in_grp % gm;
-  const int tn = in_grp / gm;
+  const int tn = in_grp / gm + g.tn0;
   const int i0 = g.row0 + tm * SC_BM;
   const int j0 = tn * SC_BN;
   const int iend = g.row0 + g.nrows;
@@ -802,26 +803,33 @@ int launch_schur_full(int n, int p, const double* a, int lda, const double* w, i
 
 // C(i, j) -= sum_k L21(i, k) W(j, k) for the lower triangle i >= j of the
 // order-(n-p) matrix C (column-major, ldc): the trailing update of a
-// right-looking factorization, rows of L21 = rows p..n-1 of the panel.
+// right-looking factorization, rows of L21 = rows p..n-1 of the panel.  Only
+// the 128-wide tile columns [tc0, tc1) of C (rows from the first of them
+// down); tc1 < 0: to the last.
 int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, int ldw,
-                       const int* nelim, double* c, int ldc, hipStream_t stream) {
+                       const int* nelim, double* c, int ldc, int tc0, int tc1, hipStream_t stream) {
+  const int r = n - p;
+  const int nt = (r + SC_BM - 1) / SC_BM;
+  if (tc1 < 0 || tc1 > nt) tc1 = nt;
+  if (tc0 < 0) tc0 = 0;
+  if (tc0 >= tc1 || p == 0) return 0;
   SchurWArgs g;
-  g.r = n - p;
+  g.r = r;
   g.l21 = a + p;
   g.lda = lda;
   g.w = w;
   g.ldw = ldw;
   g.nelim_p = nelim;
   g.p = p;
-  g.row0 = 0;
-  g.nrows = g.r;
-  g.s = c;
+  g.row0 = tc0 * SC_BM;          // rows above the first tile column's diagonal are not touched
+  g.nrows = r - g.row0;
+  g.s = c + g.row0;              // the subtracting epilogue indexes rows from row0
   g.lds = ldc;
   g.tiled = 0;
-  g.ntm = (g.r + SC_BM - 1) / SC_BM;
-  g.ntn = g.ntm;
+  g.tn0 = tc0;
+  g.ntm = (g.nrows + SC_BM - 1) / SC_BM;
+  g.ntn = tc1 - tc0;
   const int total = g.ntm * g.ntn;
-  if (total == 0 || p == 0) return 0;
   g.per_xcd = (total + SC_NXCD - 1) / SC_NXCD;
   const unsigned grid = g.per_xcd * SC_NXCD;
   const bool vec = ((reinterpret_cast<uintptr_t>(a + p) | reinterpret_cast<uintptr_t>(w)) % 16 == 0) &&

@@ -45,6 +45,7 @@ CSRC = os.path.join(ROOT, "paper_1305_2353_amd", "csrc")
 KERNELS = ["compress", "pivot", "tpp"]
 METHOD = {"tpp": 0, "strict": 1, "relaxed": 2, "restricted": 3}
 FLAG_ROOT, FLAG_ONE_WG = 1, 2
+STATUS_RELAXED_RESCAN = 4
 COMMON = ["-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer", "-fno-strict-aliasing", "-ffp-contract=off",
           "-Wno-unknown-pragmas", "-pthread", "-I", os.path.join(HERE, "host_emu")]
 SANITIZERS = {"asan": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
@@ -87,11 +88,17 @@ def binaries(tmp_path_factory):
 
 
 def _panel(case):
-    n, p, method, flags, seed, zero_cols = case
+    n, p, method, flags, seed, extra = case
     A = supernode(n, p, seed=seed, n_small=min(4, p))
-    for j in zero_cols:            # exactly zero columns of the panel: zero pivots
-        A[:, j] = 0.0
-        A[j, :p] = 0.0
+    if extra == "rank1":
+        # A21 dominated by a rank-one term: every column ranks the rows
+        # alike, so the relaxed lists run out and columns are rescanned
+        rng = np.random.default_rng(seed)
+        A[p:] += 100.0 * np.outer(rng.standard_normal(n - p), rng.standard_normal(p))
+    else:
+        for j in extra:            # exactly zero columns of the panel: zero pivots
+            A[:, j] = 0.0
+            A[j, :p] = 0.0
     return A
 
 
@@ -131,10 +138,12 @@ def _check(case, g):
     assert np.array_equal(np.tril(g["out"][:p]), np.tril(ref.out[:p])), case
     if method == "tpp":
         assert np.array_equal(g["out"][p:], ref.out[p:]), case
+    if case[5] == "rank1":
+        assert g["status"] & STATUS_RELAXED_RESCAN, "the rank-one panel should need rescans"
     return "ok"
 
 
-# (n, p, method, flags, seed, zero columns)
+# (n, p, method, flags, seed, zero columns or "rank1")
 ASAN_CASES = [
     (256, 32, "relaxed", 0, 0, ()),                 # decide/apply, 256 threads
     (256, 32, "strict", 0, 0, ()),
@@ -146,12 +155,14 @@ ASAN_CASES = [
     (600, 48, "tpp", 0, 4, ()),                     # grid-wide TPP, 9 workgroups
     (200, 24, "relaxed", 0, 5, (3, 11)),            # zero pivots
     (40, 24, "tpp", FLAG_ROOT, 6, ()),              # root panel
+    (1500, 32, "relaxed", 0, 9, "rank1"),           # relaxed rescans
 ]
 TSAN_CASES = [
     (256, 32, "relaxed", 0, 0, ()),
     (256, 32, "strict", 0, 0, ()),
     (256, 32, "tpp", 0, 0, ()),
     (300, 32, "tpp", FLAG_ONE_WG, 2, ()),
+    (1500, 32, "relaxed", 0, 9, "rank1"),
 ]
 LARGE_CASES = [
     (300, 130, "relaxed", 0, 7, ()),                # decide/apply, 512 threads
