@@ -224,6 +224,39 @@ def accept_2x2(a_tt, a_tm, a_mm, maxt, maxm, u, small):
     return (g_t <= inv_u) and (g_m <= inv_u), margins
 
 
+def reject_2x2_early(a_tt, a_tm, a_mm, maxm, u, small):
+    """The 2x2 test of eq. (2.2) decided without maxt, where its outcome is
+    already fixed: True when the pair is certainly rejected.  (The paper
+    evaluates the test with both maxima; skipping column t where the
+    outcome cannot depend on it changes no decision, only which entries the
+    search reads.)
+
+    The acceptance test (accept_2x2) fails whatever maxt >= 0 is when the
+    scaled determinant fails its test, or when the term of a component of
+    |D^-1| (maxt, maxm)^T that does not involve maxt already exceeds 1/u:
+    the other term is nonnegative, and the rounded sum of nonnegative terms
+    is at least each of them.  With maxm below small the small-column branch
+    of the test may accept, so nothing is decided there.  The search then
+    does not read column t at all (so its entries do not reach the
+    non-finite status bit).
+    """
+    big = max(abs(a_tt), abs(a_tm), abs(a_mm))
+    if big < small:
+        return True
+    s = 1 / big
+    det1 = (a_tm * s) * a_tm
+    det0 = (a_mm * s) * a_tt
+    det = det0 - det1
+    bound = max(small, abs(det0) / 2, abs(det1) / 2)
+    if abs(det) <= bound:
+        return True
+    if not maxm >= small:
+        return False
+    f = s / abs(det)
+    inv_u = 1 / u
+    return (f * abs(a_tm)) * maxm > inv_u or (f * abs(a_tt)) * maxm > inv_u
+
+
 def det_ok(a_tt, a_tm, a_mm, small):
     """The non-singularity part of the 2x2 test alone (Section 2; reading
     C2/C3): scaled determinant clear of cancellation and of small."""
@@ -447,15 +480,18 @@ def factor_trapezoid(A11, R, u=0.01, small=1e-20, r_update=R_NORMAL, forced=None
             # Partner t: largest |a(m, j)| over the pending columns nelim..m-1.
             row = np.abs(T[m, nelim:m])
             t = nelim + int(np.argmax(row))
-            if not (_finite(row) and _finite(T[t, t]) and _finite(_col_values(T, R, nelim, t, {t}))):
+            maxm = _absmax(_col_values(T, R, nelim, m, {t, m}), zero)
+            # column t is read only when the test needs maxt
+            early = _finite(row) and reject_2x2_early(T[t, t], T[m, t], T[m, m], maxm, u, small)
+            if not (_finite(row) and _finite(T[t, t]) and (early or _finite(_col_values(T, R, nelim, t, {t})))):
                 status |= ST_NONFINITE
             margins = {}
             if row.size > 1:
                 srt = sorted((float(v) for v in row), reverse=True)
                 margins["t_gap"] = _ratio_margin(srt[0], srt[1]) if srt[1] > 0 else float("inf")
             maxt = _absmax(_col_values(T, R, nelim, t, {t, m}), zero)
-            maxm = _absmax(_col_values(T, R, nelim, m, {t, m}), zero)
             ok, mg = accept_2x2(T[t, t], T[m, t], T[m, m], maxt, maxm, u, small)
+            assert not (early and ok), "an early rejection must agree with the full test"
             margins.update(mg)
             vals2 = {"t": int(perm[t]), "a_tt": T[t, t], "a_tm": T[m, t],
                      "a_mm": T[m, m], "maxt": maxt, "maxm2": maxm}

@@ -478,6 +478,27 @@ enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT };
 // reduced values and keeps its own copy, so a rejected candidate costs only
 // its reductions.  Barriers per elimination: one between the row and the
 // column half of the interchanges, one at the end.
+// Before pass B: is the pair (partner t = ri, candidate m) rejected by the
+// 2x2 test whatever column t holds?  Every thread evaluates the same bits:
+// a_tt lazily from the square, |a_tm| = rv from the partner search, column
+// m's maximum over rows other than m and t from its column buffer.  Then
+// column t is not scanned and the 1x1 test decides; a non-finite a_tt is
+// still reported (it was read).  On a rejection the workgroup meets before
+// returning: what follows (the interchanges) rewrites the LDS entries read
+// here.  The decision is the same in every thread, since all read the same
+// values before that barrier.
+CTP_DEV bool reject_early(const PivotArgs& g, int ns, int ri, double rv, double amm, const Top2& cm, int cA,
+                          double inv_u) {
+  if (!(rv >= 0.0)) return false;   // no finite partner value
+  const double att = lazy_a(g, ns, ri, ri);
+  const bool early = reject_2x2_early(att, rv, amm, top2_excluding(cm, fabs(pv_dyn[cA + ri])), g.small, inv_u);
+  if (early) {
+    if (nonfinite(att) && threadIdx.x == 0) atomicOr(&pv_sh.status, ST_NONFINITE);
+    __syncthreads();
+  }
+  return early;
+}
+
 template <int NT>
 CTP_DEV void pivot_decide_body(const PivotArgs& g) {
   const int p = g.p;
@@ -588,7 +609,7 @@ CTP_DEV void pivot_decide_body(const PivotArgs& g) {
       const double colmax = fmax(fabs(amm), maxm);
       if (colmax < g.small) {
         action = ACT_ZERO;
-      } else if (m > nelim) {
+      } else if (m > nelim && !reject_early(g, ns, ri, rv, amm, cm, cA, inv_u)) {
         t = ri;
         // pass B: column t (rows other than t) into colB with its largest
         // two; a_tt (thread 0), a_mt (the owner of row m) and a_tm (read

@@ -78,6 +78,27 @@ CTP_DEV bool accept_2x2(double att, double atm, double amm, double maxt, double 
   return (gt <= inv_u) && (gm <= inv_u);
 }
 
+// The 2x2 test above decided before column t's maximum is known, where its
+// outcome cannot depend on it: true when the pair is rejected for every
+// maxt >= 0 (the determinant test fails, or a term of |D^-1| (maxt, maxm)
+// without maxt already exceeds 1/u: the rounded sum with a nonnegative term
+// is at least that term).  With maxm below small the small-column branch
+// may still accept, so nothing is decided.  The same comparisons as
+// accept_2x2, so an early rejection is one that accept_2x2 would give.
+CTP_DEV bool reject_2x2_early(double att, double atm, double amm, double maxm, double small, double inv_u) {
+  const double big = fmax(fmax(fabs(att), fabs(atm)), fabs(amm));
+  if (big < small) return true;
+  const double s = 1.0 / big;
+  const double det1 = (atm * s) * atm;
+  const double det0 = (amm * s) * att;
+  const double det = det0 - det1;
+  const double bound = fmax(fmax(small, fabs(det0) / 2.0), fabs(det1) / 2.0);
+  if (!(fabs(det) > bound)) return true;
+  if (!(maxm >= small)) return false;
+  const double f = s / fabs(det);
+  return (f * fabs(atm)) * maxm > inv_u || (f * fabs(att)) * maxm > inv_u;
+}
+
 // D^-1 of the 2x2 pivot [d1 d21; d21 d2] (scaled by the largest entry).
 CTP_DEV void inverse_2x2(double d1, double d21, double d2, double& i11, double& i21, double& i22) {
   const double s = 1.0 / fmax(fmax(fabs(d1), fabs(d21)), fabs(d2));

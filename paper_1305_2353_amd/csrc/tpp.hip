@@ -222,15 +222,18 @@ CTP_DEV Top2 tpp_reduce_top2(Top2 t, int slot) {
   return r;
 }
 
-CTP_DEV bool tpp_any(bool x) {
+// OR of x over the workgroup (every thread returns it).
+CTP_DEV int tpp_or(int x) {
   if (threadIdx.x == 0) tp_flag[0] = 0;
   __syncthreads();
-  if (x) tp_flag[0] = 1;
+  if (x) atomicOr(&tp_flag[0], x);
   __syncthreads();
-  const bool r = tp_flag[0] != 0;
+  const int r = tp_flag[0];
   __syncthreads();
   return r;
 }
+
+CTP_DEV bool tpp_any(bool x) { return tpp_or(x ? 1 : 0) != 0; }
 
 // Partner of the candidate at position m: the largest |a(m, j)| over the
 // pending positions nelim..m-1 (row m, lazily), ties to the lowest position.
@@ -414,7 +417,8 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
       const double* pt = g.part + (size_t)q * TPP_PART;
       top2_merge(cmr, pt[0], pt[1]);
       top2_merge(ctr, pt[2], pt[3]);
-      cmr.bad |= pt[4] != 0.0 || pt[5] != 0.0;
+      cmr.bad |= pt[4] != 0.0;
+      ctr.bad |= pt[5] != 0.0;
     }
     // the rows of the square: column m over rows other than m, column t
     // over rows other than t
@@ -426,7 +430,11 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
     const Top2 cm = tpp_reduce_top2(cmr, 0);
     const Top2 ct = tpp_reduce_top2(ctr, 1);
     const double amm = tpp_lazy_t(g, S, vm, vm, ns);
-    bad = tpp_any(cm.bad || ct.bad) || nonfinite(amm);
+    // column t counts as read (for the non-finite status) only where the
+    // 2x2 test needs its maximum, as in the one-workgroup search
+    const int anybad = tpp_or((cm.bad ? 1 : 0) | (ct.bad ? 2 : 0));
+    const bool tbad = (anybad & 2) != 0;
+    bad = (anybad & 1) != 0 || nonfinite(amm);
     const double colmax = fmax(fabs(amm), top2_max(cm));
     if (colmax < g.small) {
       action = TPP_ZERO;
@@ -437,6 +445,7 @@ CTP_DEV void tpp_decide(const TppArgs& g) {
       bad |= nonfinite(att);
       const double maxt = top2_excluding(ct, fabs(atm));
       const double maxm2 = top2_excluding(cm, fabs(xtm));
+      if (!reject_2x2_early(att, atm, amm, maxm2, g.small, inv_u)) bad |= tbad;
       if (accept_2x2(att, atm, amm, maxt, maxm2, g.small, inv_u)) {
         action = TPP_2X2;
         d1 = att;
