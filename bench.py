@@ -309,6 +309,22 @@ def batch_section(count=4096, seed=0, method="relaxed", reps=3, samples=64):
             "autotune": tune["best"], "graph": True, "oracle_sample": check}
 
 
+def probe_section():
+    """Peaks measured on this GPU by the roofline probes (register-only
+    matrix-core loops of the instructions the kernels use, a 16-byte stream
+    copy), beside the datasheet figures the roofline fractions use."""
+    from paper_1305_2353_amd import probes
+    out = {}
+    for dtype, sheet in (("fp64", PEAK_FP64_TFLOPS), ("fp32", 157.3), ("bf16", 2500.0)):
+        tf = probes.mfma_peak(dtype)
+        out[f"mfma_{dtype}_tflops"] = round(tf, 1)
+        out[f"mfma_{dtype}_of_datasheet"] = round(tf / sheet, 3)
+    gbs = probes.copy_bandwidth()
+    out["hbm_copy_gbs"] = round(gbs, 0)
+    out["hbm_copy_of_datasheet"] = round(gbs / PEAK_HBM_GBS, 3)
+    return out
+
+
 def autograd_section(S=256, N=1024, nrhs=4, pw=256, seed=0, reps=3, check=4):
     """Batched differentiable solve x = A^-1 b of S systems Q diag(lam) Q^T
     (|lam| in [1e-2, 1]) with loss sum(w * x): forward = batched
@@ -389,7 +405,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--dense-n", type=int, default=16384)
     ap.add_argument("--no-autograd", action="store_true", help="skip the batched autograd section")
-    ap.add_argument("--section", default="all", choices=["all", "supernode", "dense", "batch", "autograd"],
+    ap.add_argument("--no-probes", action="store_true", help="skip the roofline probes (measured peaks)")
+    ap.add_argument("--section", default="all", choices=["all", "supernode", "dense", "batch", "autograd", "probes"],
                     help="run one part alone (for profiling): the supernode step (with the TPP "
                          "comparison unless --no-tpp), the dense section or the batch section")
     args = ap.parse_args()
@@ -413,6 +430,9 @@ def main():
         return
     if args.section == "autograd":
         print(json.dumps({"autograd": autograd_section()}), flush=True)
+        return
+    if args.section == "probes":
+        print(json.dumps({"measured_peaks": probe_section()}), flush=True)
         return
     if args.section == "supernode":
         args.no_dense = args.no_batch = args.no_autograd = True
@@ -544,6 +564,11 @@ def main():
                          "factor_solve_ms": round(tpp_ms, 3), "nelim": int(tf["nelim"].item()),
                          "compressed_factor_solve_ms": round(cmp_ms, 3),
                          "speedup_compressed_vs_tpp": round(tpp_ms / cmp_ms, 2) if cmp_ms > 0 else None}
+
+    if not args.no_probes:
+        peaks = probe_section()
+        result["measured_peaks"] = peaks
+        result["roofline"]["frac_of_measured_peak"] = round(achieved / peaks["mfma_fp64_tflops"], 4)
 
     if not args.no_dense:
         result["dense"] = dense_section(args.dense_n)

@@ -3,7 +3,8 @@
     python -m paper_1305_2353_amd.build
 
 Every source under csrc/ is compiled on each call (a few seconds each) and
-linked into paper_1305_2353_amd/libctp.so.
+linked into paper_1305_2353_amd/libctp.so; the roofline probes under probe/
+go into paper_1305_2353_amd/libctp_probe.so.
 """
 
 import os
@@ -16,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libctp.so")
+PROBE_SRC = os.path.join(HERE, "probe", "probe.hip")
+PROBE_OUT = os.path.join(HERE, "libctp_probe.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 ARCH = "gfx950"
@@ -54,7 +57,21 @@ def build(verbose=False):
     shutil.move(tmp, OUT)
     if verbose:
         print(f"built {OUT}")
+    build_probe(verbose)
     return OUT
+
+
+def build_probe(verbose=False):
+    """The roofline probes (measured peaks), a library of their own."""
+    tmp = PROBE_OUT + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", PROBE_SRC, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PROBE_SRC}:\n{res.stdout}\n{res.stderr}")
+    shutil.move(tmp, PROBE_OUT)
+    if verbose:
+        print(f"built {PROBE_OUT}")
+    return PROBE_OUT
 
 
 if __name__ == "__main__":
