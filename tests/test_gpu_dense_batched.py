@@ -57,16 +57,28 @@ def test_batched_dense_matches_oracle_and_single_driver(method, S, N, pw, n_smal
     from paper_1305_2353_amd import ctp
     _announce("dense batched", method, S, N, pw)
     As = [_sym(N, seed=N + pw + 7 * s, n_small=n_small) for s in range(S)]
-    refs = []
-    for A in As:
+    opts = ctp.ctp_default_opts(method)
+    refs, too_wide = [], []
+    for s, A in enumerate(As):
         try:
             ref = ldlt_dense(A, pw, method)
         except ValueError:
-            pytest.skip("a panel of this draw would pass 512 columns")
+            too_wide.append(s)          # delays grow a panel past 512 columns
+            continue
         if ref.fragile:
             pytest.skip("near-tie decision in this draw")
         refs.append(ref)
-    opts = ctp.ctp_default_opts(method)
+    if too_wide:
+        # (strict pivoting on the N = 700 draws: its delays pile up) both
+        # drivers refuse with CTP_ERR_PANEL_TOO_WIDE where the oracle does
+        work = ctp.dense_batched_workspace(S, N, pw, opts)
+        with pytest.raises(ctp.CtpError, match=str(ctp.CTP_ERR_PANEL_TOO_WIDE)):
+            ctp.ctp_ldlt_dense_batched(_batch(As), pw, opts, work)
+        for s in too_wide:
+            with pytest.raises(ctp.CtpError, match=str(ctp.CTP_ERR_PANEL_TOO_WIDE)):
+                _single(As[s], pw, opts)
+        torch.cuda.synchronize()
+        return
     a = _batch(As)
     work = ctp.dense_batched_workspace(S, N, pw, opts)
     f = ctp.ctp_ldlt_dense_batched(a, pw, opts, work)
