@@ -1,7 +1,10 @@
 """Differentiable solve x = A^-1 b (paper_1305_2353_amd.autograd) on the GPU:
 analytic gradients against the oracle's adjoint, and directional
-derivatives against central finite differences computed with the GPU solve
-itself (one FP64 refinement step per forward solve, h = 1e-6)."""
+derivatives against finite differences computed with the GPU solve itself
+(fourth-order central differences, h = 1e-3, each forward solve refined in
+FP64: the error of this scheme on these matrices, |lambda| >= 1e-2, is
+about 1e-10 to 1e-9; the plain two-point difference at h = 1e-6 with one refinement
+step stops near 4e-7)."""
 
 import numpy as np
 import pytest
@@ -69,16 +72,19 @@ def test_directional_derivatives_match_finite_differences():
         a0 = ctp.device_panel(M)
         work = ctp.dense_workspace(N, pw, opts, nrhs)
         f = ctp.ctp_ldlt_dense(a, pw, opts, work)
-        x, steps, hist = ctp.ctp_ldlt_refine(a0, a, f, ctp.device_panel(B0), opts, work, tol=0.0, max_steps=1)
+        x, steps, hist = ctp.ctp_ldlt_refine(a0, a, f, ctp.device_panel(B0), opts, work, tol=0.0, max_steps=3)
         return float((W * x.cpu().numpy()).sum())
 
-    h = 1e-6
+    h = 1e-3
     worst = 0.0
     for _ in range(32):
         Z = rng.standard_normal((N, N))
         E = (Z + Z.T) / 2
         E /= np.linalg.norm(E)
-        fd = (loss(A0 + h * E) - loss(A0 - h * E)) / (2 * h)
+        d1 = loss(A0 + h * E) - loss(A0 - h * E)
+        d2 = loss(A0 + 2 * h * E) - loss(A0 - 2 * h * E)
+        fd = (8 * d1 - d2) / (12 * h)
         an = float((G * E).sum())
         worst = max(worst, abs(fd - an) / max(abs(an), 1e-3))
-    assert worst < 1e-5, worst
+    print(f"worst relative error of the directional derivatives: {worst:.2e}", flush=True)
+    assert worst < 1e-8, worst
