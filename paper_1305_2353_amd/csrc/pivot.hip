@@ -473,11 +473,6 @@ CTP_DEV void swap_rows(const PivotArgs& g, int ns, const SwapPlan& s) {
 
 enum { ACT_NONE = 0, ACT_ZERO, ACT_2X2, ACT_1X1, ACT_REJECT };
 
-// The pivot loop.  Its state (nelim, m, progress, the number of pending
-// slots) is uniform: every thread takes the same decisions from the same
-// reduced values and keeps its own copy, so a rejected candidate costs only
-// its reductions.  Barriers per elimination: one between the row and the
-// column half of the interchanges, one at the end.
 // Before pass B: is the pair (partner t = ri, candidate m) rejected by the
 // 2x2 test whatever column t holds?  Every thread evaluates the same bits:
 // a_tt lazily from the square, |a_tm| = rv from the partner search, column
@@ -499,6 +494,11 @@ CTP_DEV bool reject_early(const PivotArgs& g, int ns, int ri, double rv, double 
   return early;
 }
 
+// The pivot loop.  Its state (nelim, m, progress, the number of pending
+// slots) is uniform: every thread takes the same decisions from the same
+// reduced values and keeps its own copy, so a rejected candidate costs only
+// its reductions.  Barriers per elimination: one between the row and the
+// column half of the interchanges, one at the end.
 template <int NT>
 CTP_DEV void pivot_decide_body(const PivotArgs& g) {
   const int p = g.p;
