@@ -79,7 +79,10 @@ extern "C" {
 /* Device status bits. */
 #define CTP_STATUS_ZERO_PIVOT 1     /* a zero pivot was recorded */
 #define CTP_STATUS_NONFINITE 2      /* a NaN/Inf was read by a pivot test or by the compression */
-#define CTP_STATUS_RELAXED_RESCAN 4 /* relaxed C needed a full column rescan */
+#define CTP_STATUS_RELAXED_RESCAN 4 /* relaxed C needed a full column rescan (only panels of
+                                       more than 16384 A21 rows, and the batched calls, walk
+                                       top-8 candidate lists that can run out; a diagnostic
+                                       of the search, not of C) */
 #define CTP_STATUS_ROOT_FALLBACK 8  /* CTP_FLAG_ROOT: a column was eliminated regardless of u */
 #define CTP_STATUS_BAD_MAP 16       /* extend-add: a map or perm entry out of range (entry skipped) */
 

@@ -150,9 +150,13 @@ int ctp_compress(int n, int p, const double* a, int lda, int method, double* c, 
   return launch_compress(n, p, a, lda, method, c, ldc, crow, status, work, stream);
 }
 
-int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
-                         double* d, int* nelim, int* status, void* work, size_t lwork,
-                         hipStream_t stream) {
+// The Factor task with a host hook that runs once the compression kernels
+// (if the rule has any) are enqueued, before the pivot search: the dense
+// driver starts the previous panel's deferred trailing update there, so that
+// the compression's workgroups do not wait behind that update's.
+static int factor_supernode_hooked(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                                   double* d, int* nelim, int* status, void* work, size_t lwork,
+                                   hipStream_t stream, int (*hook)(void*), void* hook_arg) {
   if (n < p) return -1;
   if (p < 0) return -2;
   if (!a && n > 0 && p > 0) return -3;
@@ -188,6 +192,7 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
     ldr = lda;
     rrows = r;
   }
+  if (hook && (rc = hook(hook_arg)) != 0) return rc;
   const int root = (opts->flags & CTP_FLAG_ROOT) ? 1 : 0;
   const int one_wg = (opts->flags & CTP_FLAG_ONE_WG) ? 1 : 0;
   if (method == CTP_TPP && r > 0 && !one_wg)
@@ -199,6 +204,13 @@ int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts,
   return launch_pivot_factor(p, a, lda, rrows, R, ldr, abs_update, root, one_wg, opts->u, opts->small, perm,
                              piv, d, nelim, status, base + ws.st_off,
                              reinterpret_cast<double*>(base + ws.wb_off), stream);
+}
+
+int ctp_factor_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                         double* d, int* nelim, int* status, void* work, size_t lwork,
+                         hipStream_t stream) {
+  return factor_supernode_hooked(n, p, a, lda, opts, perm, piv, d, nelim, status, work, lwork, stream, nullptr,
+                                 nullptr);
 }
 
 int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const int* piv,
@@ -229,13 +241,14 @@ int ctp_solve_supernode(int n, int p, double* a, int lda, const int* perm, const
   return launch_lowp_convert(n - p, p, a + p, lda, w, ws.ldw, nelim, opts->prec, base + lowp_region_off(ws), stream);
 }
 
-int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
-                  double* d, int* nelim, int* status, double* s, int lds, void* work, size_t lwork,
-                  hipStream_t stream) {
+static int supernode_hooked(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                            double* d, int* nelim, int* status, double* s, int lds, void* work, size_t lwork,
+                            hipStream_t stream, int (*hook)(void*), void* hook_arg) {
   const int r = n - p;
   const bool tiled = opts && (opts->flags & CTP_FLAG_S_TILED);
   if (s && !tiled && lds < (r > 1 ? r : 1)) return -12;
-  int rc = ctp_factor_supernode(n, p, a, lda, opts, perm, piv, d, nelim, status, work, lwork, stream);
+  int rc = factor_supernode_hooked(n, p, a, lda, opts, perm, piv, d, nelim, status, work, lwork, stream, hook,
+                                   hook_arg);
   if (rc) return rc == -12 ? -13 : rc;
   rc = ctp_solve_supernode(n, p, a, lda, perm, piv, d, nelim, opts, work, lwork, stream);
   if (rc) return rc == -11 ? -13 : rc;
@@ -246,6 +259,13 @@ int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* p
                             static_cast<unsigned char*>(work) + lowp_region_off(ws), stream);
   const double* w = reinterpret_cast<const double*>(static_cast<const unsigned char*>(work) + ws.w_off);
   return launch_schur_full(n, p, a, lda, w, ws.ldw, nelim, s, lds, tiled ? 1 : 0, 0, stream);
+}
+
+int ctp_supernode(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
+                  double* d, int* nelim, int* status, double* s, int lds, void* work, size_t lwork,
+                  hipStream_t stream) {
+  return supernode_hooked(n, p, a, lda, opts, perm, piv, d, nelim, status, s, lds, work, lwork, stream, nullptr,
+                          nullptr);
 }
 
 int ctp_supernode_noalloc(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv,
@@ -490,3 +510,13 @@ int ctp_extend_add_batched(int count, const ctp_scatter_task* tasks, long long t
 }
 
 }  // extern "C"
+
+namespace ctp {
+// ctp_supernode with the host hook of factor_supernode_hooked (dense driver).
+int supernode_with_hook(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv, double* d,
+                        int* nelim, int* status, void* work, size_t lwork, hipStream_t stream,
+                        int (*hook)(void*), void* hook_arg) {
+  return supernode_hooked(n, p, a, lda, opts, perm, piv, d, nelim, status, nullptr, 0, work, lwork, stream, hook,
+                          hook_arg);
+}
+}  // namespace ctp

@@ -15,14 +15,16 @@
 // Relaxed (Section 4.2): row j of C is the largest unflagged entry's row
 //   of column j, taken in column order with flagging.  The row chosen for
 //   column j is the best of column j once at most j rows are excluded, so
-//   it is among column j's top j+1 rows.  Pass 1 keeps, per (column, row
+//   it is among column j's top j+1 rows.  Panels of at most EXACT_MAX_R
+//   rows give every column exactly that list (below, with the kernels that
+//   build and walk it).  Taller panels: pass 1 keeps, per (column, row
 //   chunk), the top RELAXED_TOPK (|a|, row) pairs in the total order
 //   "larger value first, lower row first"; pass 2 (one workgroup) merges
 //   them per column, walks the columns in order taking the first unflagged
 //   candidate, rescans a column in full when all its candidates are taken
 //   (rare on random panels; common on Schur complements dominated by a
-//   low-rank term, whose columns all rank the rows alike), and gathers the
-//   chosen signed rows into C.
+//   low-rank term, whose columns all rank the rows alike).  Either walk
+//   ends with the chosen signed rows gathered into C.
 
 #include "common.h"
 
@@ -124,7 +126,7 @@ struct Cand {
   int i;      // row of A21
 };
 
-static size_t relaxed_flag_bytes(int r) { return (size_t)((r > 0 ? r : 1) + 31) / 32 * sizeof(unsigned); }
+__host__ __device__ inline size_t relaxed_flag_bytes(int r) { return (size_t)((r > 0 ? r : 1) + 31) / 32 * sizeof(unsigned); }
 
 CTP_DEV bool better(double v1, int i1, double v2, int i2) {
   return v1 > v2 || (v1 == v2 && i1 < i2);
@@ -393,6 +395,264 @@ __global__ __launch_bounds__(1024) void relaxed_select_kernel(int r, int p, cons
 }
 
 // ---------------------------------------------------------------------------
+// Relaxed compression with exact candidate lists (r <= EXACT_MAX_R rows).
+//
+// The row chosen for column j is column j's best row once at most j rows
+// are excluded, so it is always among column j's top j+1 rows.  For panels
+// of up to EXACT_MAX_R rows each column gets exactly those: min(j+1, r) row
+// indices, best first, at offset j(j+1)/2 of a list array (16-bit rows).
+// The walk then never runs out of candidates and never rescans a column,
+// which matters on Schur complements dominated by a low-rank term, where
+// every column ranks the rows alike and the top-8 lists above are
+// exhausted from the ninth column on.
+//
+// Build (one workgroup per column, up to 16 rows per thread in registers,
+// 64 to 1024 threads by the panel's height): the order "larger |a| first, lower row first" is the order of
+// the 77-bit key (bits 62..0 of |a| as an integer, EXACT_MAX_R-1-row).  A
+// most-significant-digit radix select narrows the key range that holds the
+// (j+1)-th key, digit by digit (8-bit digits of |a|, then 7-bit digits of
+// the row), until the keys at or above the range's lower end number at most
+// EXACT_CAP; those are collected in LDS, sorted by a bitonic network and
+// the first j+1 written out.  The keys are distinct, so after the last digit
+// the range holds one key and at most j+1 <= EXACT_CAP are collected.
+// ---------------------------------------------------------------------------
+
+constexpr int EXACT_MAX_R = 16384;                     // rows of A21 the exact lists are built for
+constexpr int EXACT_THREADS = 1024;
+constexpr int EXACT_PER_THREAD = EXACT_MAX_R / EXACT_THREADS;
+constexpr int EXACT_CAP = 1024;                        // keys sorted at the end (>= 2 * CTP_MAX_P)
+constexpr size_t EXACT_WALK_LDS = 128 * 1024;          // lists copied to LDS for the walk up to this size
+
+static_assert(EXACT_CAP >= 2 * CTP_MAX_P, "a column's list must fit the final sort");
+static_assert(EXACT_MAX_R <= 65536, "rows are stored in 16 bits");
+
+__host__ __device__ inline size_t exact_list_entries(int p, int r) {
+  const size_t m = (size_t)(p < r ? p : r);
+  return m * (m + 1) / 2;
+}
+// walk kernel's dynamic LDS: row bitmap, chosen rows, then the lists
+__host__ __device__ inline size_t exact_walk_lists_off(int p, int r) {
+  return align_up(relaxed_flag_bytes(r) + (size_t)p * sizeof(int), 16);
+}
+__host__ __device__ inline size_t exact_walk_lds(int p, int r, bool lds_lists) {
+  return exact_walk_lists_off(p, r) + (lds_lists ? align_up(exact_list_entries(p, r) * sizeof(unsigned short), 16) : 0);
+}
+
+// key a before key b in the selection order
+CTP_DEV bool key_before(unsigned long long ka, int ia, unsigned long long kb, int ib) {
+  return ka > kb || (ka == kb && ia < ib);
+}
+
+__global__ __launch_bounds__(EXACT_THREADS) void relaxed_exact_kernel(int r, int p, const double* __restrict__ a21,
+                                                                     int lda, unsigned short* __restrict__ lists,
+                                                                     int* __restrict__ status) {
+  __shared__ unsigned hist[256];
+  __shared__ unsigned long long sk[EXACT_CAP];
+  __shared__ int si[EXACT_CAP];
+  __shared__ unsigned s_digit, s_add, s_bin;
+  __shared__ int s_cnt;
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
+  const double* colp = a21 + (size_t)j * lda;
+
+  unsigned long long key[EXACT_PER_THREAD];
+  bool finite = true;
+#pragma unroll
+  for (int u = 0; u < EXACT_PER_THREAD; ++u) {
+    const int i = tid + u * nthr;
+    const double v = i < r ? fabs(colp[i]) : 0.0;
+    finite = finite && isfinite(v);
+    key[u] = (unsigned long long)__double_as_longlong(v);
+  }
+  if (!finite) atomicOr(status, ST_NONFINITE);
+  if (j >= r) return;               // every row is taken before column j (uniform over the workgroup)
+  const unsigned K = (unsigned)min(j + 1, r);
+
+  // Range of the (j+1)-th key: keys whose masked fields equal (hp, lp).
+  unsigned long long hp = 0, hm = 0;
+  unsigned lp = 0, lm = 0;
+  unsigned need = K;                // keys still to take from the range
+  unsigned above = 0;               // keys above the range
+  for (int pass = 0; pass < 10; ++pass) {
+    const bool hi_field = pass < 8;
+    const int shift = pass < 7 ? 55 - 8 * pass : pass == 7 ? 0 : pass == 8 ? 7 : 0;
+    const unsigned wmask = pass < 7 ? 0xffu : 0x7fu;
+    for (int q = tid; q < 256; q += nthr) hist[q] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < EXACT_PER_THREAD; ++u) {
+      const int i = tid + u * nthr;
+      const unsigned lo = (unsigned)(EXACT_MAX_R - 1 - i);
+      const bool m = i < r && (key[u] & hm) == hp && (lo & lm) == lp;
+      const unsigned dg = hi_field ? (unsigned)(key[u] >> shift) & wmask : (lo >> shift) & wmask;
+      // one atomic per wave when its matching keys share the digit (the
+      // leading digits of similar values), one per key otherwise
+      const unsigned long long bal = __ballot(m);
+      if (bal) {
+        const int first = __ffsll((long long)bal) - 1;
+        const unsigned d0 = __shfl(dg, first, 64);
+        const unsigned long long same = __ballot(m && dg == d0);
+        if (same == bal) {
+          if (lane == first) atomicAdd(&hist[d0], (unsigned)__popcll(bal));
+        } else if (m) {
+          atomicAdd(&hist[dg], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // lane l owns digits 255-4l .. 252-4l (descending); an inclusive scan
+      // over the lanes finds the digit that holds the need-th key
+      const unsigned h0 = hist[255 - 4 * lane], h1 = hist[254 - 4 * lane];
+      const unsigned h2 = hist[253 - 4 * lane], h3 = hist[252 - 4 * lane];
+      const unsigned s = h0 + h1 + h2 + h3;
+      unsigned inc = s;
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned o = __shfl(inc, lane >= off ? lane - off : lane, 64);
+        if (lane >= off) inc += o;
+      }
+      const unsigned exc = inc - s;
+      if (exc < need && need <= inc) {
+        // the first of the lane's four digits whose running count reaches need
+        const unsigned c1 = exc + h0, c2 = c1 + h1, c3 = c2 + h2;
+        const int t = need <= c1 ? 0 : need <= c2 ? 1 : need <= c3 ? 2 : 3;
+        s_digit = (unsigned)(255 - 4 * lane - t);
+        s_add = t == 0 ? exc : t == 1 ? c1 : t == 2 ? c2 : c3;
+        s_bin = t == 0 ? h0 : t == 1 ? h1 : t == 2 ? h2 : h3;
+      }
+    }
+    __syncthreads();
+    const unsigned d = s_digit;
+    need -= s_add;
+    above += s_add;
+    if (hi_field) {
+      hp |= (unsigned long long)d << shift;
+      hm |= (unsigned long long)wmask << shift;
+    } else {
+      lp |= d << shift;
+      lm |= wmask << shift;
+    }
+    if (above + s_bin <= (unsigned)EXACT_CAP) break;   // uniform: every thread read the same values
+  }
+
+  // Collect the keys at or above the range's lower end (above + s_bin of them).
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < EXACT_PER_THREAD; ++u) {
+    const int i = tid + u * nthr;
+    const unsigned lo = (unsigned)(EXACT_MAX_R - 1 - i);
+    bool ge;
+    if (lm == 0u) ge = (key[u] & hm) >= hp;
+    else ge = key[u] > hp || (key[u] == hp && (lo & lm) >= lp);
+    if (i < r && ge) {
+      const int slot = atomicAdd(&s_cnt, 1);
+      if (slot < EXACT_CAP) { sk[slot] = key[u]; si[slot] = i; }
+    }
+  }
+  __syncthreads();
+  const int cnt = min(s_cnt, EXACT_CAP);
+  int n2 = 1;
+  while (n2 < cnt) n2 <<= 1;
+  for (int q = cnt + tid; q < n2; q += nthr) { sk[q] = 0ull; si[q] = 0x7fffffff; }   // sorts last
+  __syncthreads();
+  // bitonic sort of n2 keys into selection order
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int t = tid; t < n2; t += nthr) {
+        const int o = t ^ jj;
+        if (o > t) {
+          const unsigned long long kt = sk[t], ko = sk[o];
+          const int it = si[t], io = si[o];
+          const bool fwd = (t & k) == 0;
+          if (fwd ? key_before(ko, io, kt, it) : key_before(kt, it, ko, io)) {
+            sk[t] = ko; si[t] = io;
+            sk[o] = kt; si[o] = it;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  unsigned short* out = lists + (size_t)j * (j + 1) / 2;
+  for (int q = tid; q < (int)K; q += nthr) out[q] = (unsigned short)si[q];
+}
+
+// One workgroup; wave 0 walks the columns in order and takes the first row
+// of column j's list not taken yet (there is one: the list holds j+1
+// distinct rows and j rows are taken); lanes test 4 x 64 list entries per
+// step, and the next column's first entries are read while the flags of
+// this one are tested.  The choices stay in LDS until the walk ends.  Dynamic LDS: a bitmap
+// of the rows taken, the chosen rows (p ints), then (LDS_LISTS) the lists,
+// 16-byte aligned.
+template <bool LDS_LISTS>
+__global__ __launch_bounds__(1024) void relaxed_walk_kernel(int r, int p, const unsigned short* __restrict__ lists,
+                                                          int* __restrict__ crow_out) {
+  unsigned* flags = reinterpret_cast<unsigned*>(cmp_smem);
+  const int nwords = (r + 31) / 32;
+  int* chosen = reinterpret_cast<int*>(flags + nwords);
+  unsigned short* lcopy = reinterpret_cast<unsigned short*>(cmp_smem + exact_walk_lists_off(p, r));
+  const int m = min(p, r);
+  for (int q = threadIdx.x; q < nwords; q += blockDim.x) flags[q] = 0u;
+  if (LDS_LISTS) {
+    // 16-byte words (the list array starts 256-byte aligned in the workspace)
+    const size_t nw = (exact_list_entries(p, r) * sizeof(unsigned short) + 15) / 16;
+    const uint4* src4 = reinterpret_cast<const uint4*>(lists);
+    uint4* dst4 = reinterpret_cast<uint4*>(lcopy);
+    for (size_t q = threadIdx.x; q < nw; q += blockDim.x) dst4[q] = src4[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const unsigned short* src = LDS_LISTS ? lcopy : lists;
+    // entries c0 + lane + 64t (t < 4) of column j's list; positions past its
+    // end read the last entry and are masked when tested
+    auto load4 = [&](int j, int c0, int (&row)[4]) {
+      const unsigned short* L = src + (size_t)j * (j + 1) / 2;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) row[t] = (int)L[min(c0 + 64 * t + lane, j)];
+    };
+    int ahead[4] = {0, 0, 0, 0};
+    if (m > 0) load4(0, 0, ahead);
+    for (int j = 0; j < p; ++j) {
+      int pick = -1;
+      if (j < m) {                           // else every row is taken
+        int row[4] = {ahead[0], ahead[1], ahead[2], ahead[3]};
+        if (j + 1 < m) load4(j + 1, 0, ahead);   // the next list does not depend on the flags
+        for (int c0 = 0;;) {
+          unsigned fw[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) fw[t] = flags[(unsigned)row[t] < (unsigned)r ? row[t] >> 5 : 0];   // all four in flight
+          unsigned long long bal[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {   // bitwise, not short-circuit: no branches
+            const unsigned ok = (unsigned)(c0 + 64 * t + lane <= j) & (unsigned)((unsigned)row[t] < (unsigned)r);
+            bal[t] = __ballot((int)(ok & ~(fw[t] >> (row[t] & 31)) & 1u));
+          }
+          const int t = bal[0] ? 0 : bal[1] ? 1 : bal[2] ? 2 : bal[3] ? 3 : -1;   // uniform
+          if (t >= 0) {
+            const unsigned long long b = t == 0 ? bal[0] : t == 1 ? bal[1] : t == 2 ? bal[2] : bal[3];
+            const int rsel = t == 0 ? row[0] : t == 1 ? row[1] : t == 2 ? row[2] : row[3];
+            pick = __builtin_amdgcn_readlane(rsel, __ffsll((long long)b) - 1);
+            break;
+          }
+          c0 += 256;
+          if (c0 > j) break;                 // not reached: the list holds a free row
+          load4(j, c0, row);
+        }
+      }
+      if (lane == 0) {
+        chosen[j] = pick;
+        if (pick >= 0) atomicOr(&flags[pick >> 5], 1u << (pick & 31));   // no read round trip
+      }
+      wave_sync();   // the flag is set before any lane tests the next column
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < p; j += blockDim.x) crow_out[j] = chosen[j];
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 
@@ -419,6 +679,25 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
       hipLaunchKernelGGL(strict_colmax_kernel, dim3(grid), dim3(256), lds, stream, r, p, a21, lda, J,
                                                        reinterpret_cast<unsigned long long*>(c), ldc);
     }
+  } else if (method == CTP_RELAXED && r > 0 && r <= EXACT_MAX_R) {
+    // exact lists in the solve's gather buffer, which is free until the solve
+    unsigned short* lists = reinterpret_cast<unsigned short*>(base + ws.w_off);
+    int* rows = crow ? crow : reinterpret_cast<int*>(base + ws.crow_off);
+    const int per = (r + EXACT_PER_THREAD - 1) / EXACT_PER_THREAD;
+    const int nthr = std::min(EXACT_THREADS, std::max(64, (per + 63) / 64 * 64));
+    hipLaunchKernelGGL(relaxed_exact_kernel, dim3(p), dim3(nthr), 0, stream, r, p, a21, lda, lists, status);
+    const bool lds_lists = exact_list_entries(p, r) * sizeof(unsigned short) <= EXACT_WALK_LDS;
+    const size_t lds = exact_walk_lds(p, r, lds_lists);
+    const void* walk = lds_lists ? (const void*)relaxed_walk_kernel<true> : (const void*)relaxed_walk_kernel<false>;
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute(walk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return CTP_ERR_HIP_BASE - (int)e;
+    }
+    if (lds_lists)
+      hipLaunchKernelGGL(relaxed_walk_kernel<true>, dim3(1), dim3(1024), lds, stream, r, p, lists, rows);
+    else
+      hipLaunchKernelGGL(relaxed_walk_kernel<false>, dim3(1), dim3(1024), lds, stream, r, p, lists, rows);
+    hipLaunchKernelGGL(relaxed_gather_kernel, dim3(p, (p + 255) / 256), dim3(256), 0, stream, p, a21, lda, rows, c, ldc);
   } else if (method == CTP_RELAXED) {
     Cand* cand = reinterpret_cast<Cand*>(base + ws.cand_off);
     int nch = ws.relaxed_chunks;

@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -43,6 +44,9 @@
 
 namespace ctp {
 
+int supernode_with_hook(int n, int p, double* a, int lda, const ctp_opts* opts, int* perm, int* piv, double* d,
+                        int* nelim, int* status, void* work, size_t lwork, hipStream_t stream,
+                        int (*hook)(void*), void* hook_arg);
 int launch_schur_w_sub(int n, int p, const double* a, int lda, const double* w, int ldw,
                        const int* nelim, double* c, int ldc, int tc0, int tc1, hipStream_t stream);
 int launch_lowp_update_ops(int r, int K, const int* nelim, float* c, int ldc, int prec, void* ops, int tc0,
@@ -654,6 +658,14 @@ int ctp_dense_workspace_size(int N, int pw, const ctp_opts* opts, int nrhs_max, 
 // trailing updates that overlap it.  (Restricting stream 1 to all CUs but a
 // few, so that the chain's one-workgroup pivot search always finds a free
 // CU, measured 6 ms slower per factorization at N = 16384.)
+// Runs and clears a deferred host step (the hook of supernode_with_hook).
+static int run_deferred(void* f) {
+  auto* slot = static_cast<std::function<int()>*>(f);
+  std::function<int()> step = std::move(*slot);
+  *slot = nullptr;
+  return step ? step() : 0;
+}
+
 static hipStream_t dense_stream(int which) {
   static hipStream_t st[64][2] = {};
   static std::mutex m;
@@ -706,6 +718,7 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
     return CTP_ERR_HIP_BASE - (int)hipGetLastError();
   }
   bool rest_pending = false;
+  std::function<int()> rest_deferred;   // part 1 of the last panel's trailing update, not yet enqueued
   // every exit: the chain takes over the side stream's last work, the
   // caller's stream takes over the chain
   auto finish = [&](int code) {
@@ -740,7 +753,11 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
     if (lowp && width > carried)
       dense_from_f32_kernel<<<dim3(4, width - carried), 256, 0, stream>>>(a, lda, w32, L.ld32, k0 + carried, N);
     po.flags = opts->flags | (root ? CTP_FLAG_ROOT : 0u);
-    rc = ctp_supernode(n, width, ap, lda, &po, pperm, ppiv, pd, pnelim, pstatus, nullptr, 0, sn, L.sn_bytes, stream);
+    // the previous panel's deferred update starts once this panel's
+    // compression is enqueued (the hook), so that the compression's
+    // workgroups are not queued behind the update's
+    rc = supernode_with_hook(n, width, ap, lda, &po, pperm, ppiv, pd, pnelim, pstatus, sn, L.sn_bytes, stream,
+                             rest_deferred ? run_deferred : nullptr, &rest_deferred);
     if (rc) return finish(rc);
     int ne = 0, st = 0;
     if (hipMemcpyAsync(&ne, pnelim, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -767,33 +784,36 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
       const int nt = (r + 127) / 128;
       // tile columns holding the next panel's new columns
       const int tc = std::min(nt, (next_width - next_carried + 127) / 128);
-      if (tc < nt && hipEventRecord(ev_ready, stream) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
-      for (int part = 0; part < 2; ++part) {
-        const int t0 = part == 0 ? 0 : tc, t1 = part == 0 ? tc : nt;
-        if (t0 >= t1) continue;
-        hipStream_t s = part == 0 ? stream : side;
-        if (part == 1 && hipStreamWaitEvent(side, ev_ready, 0) != hipSuccess)
-          return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
-        if (!lowp) {
-          rc = launch_schur_w_sub(n, width, ap, lda, w, ws.ldw, pnelim,
-                                  a + (size_t)(k0 + width) * lda + (k0 + width), lda, t0, t1, s);
-        } else {
-          // the operand rows of L21 and W that the reduced-precision Solve
-          // converted into the supernode workspace
-          rc = launch_lowp_update_ops(r, width, pnelim, w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width),
+      // part 0 (the next panel's tile columns) on the chain now, part 1
+      // (the rest) on the side stream once the next panel's compression is
+      // enqueued
+      auto update = [=](int t0, int t1, hipStream_t s) {
+        if (!lowp)
+          return launch_schur_w_sub(n, width, ap, lda, w, ws.ldw, pnelim,
+                                    a + (size_t)(k0 + width) * lda + (k0 + width), lda, t0, t1, s);
+        // the operand rows of L21 and W that the reduced-precision Solve
+        // converted into the supernode workspace
+        return launch_lowp_update_ops(r, width, pnelim, w32 + (size_t)(k0 + width) * L.ld32 + (k0 + width),
                                       L.ld32, opts->prec, sn + align_up(ws.total, 256), t0, t1, s);
-        }
-        if (rc) return finish(rc);
-        if (part == 1) {
-          if (hipEventRecord(ev_rest, side) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+      };
+      if (tc > 0 && (rc = update(0, tc, stream)) != 0) return finish(rc);
+      if (tc < nt) {
+        rest_deferred = [=, &rest_pending]() {
+          if (hipEventRecord(ev_ready, stream) != hipSuccess || hipStreamWaitEvent(side, ev_ready, 0) != hipSuccess)
+            return CTP_ERR_HIP_BASE - (int)hipGetLastError();
+          const int e = update(tc, nt, side);
+          if (e) return e;
+          if (hipEventRecord(ev_rest, side) != hipSuccess) return CTP_ERR_HIP_BASE - (int)hipGetLastError();
           rest_pending = true;
-        }
+          return 0;
+        };
       }
     }
     carried = next_carried;
     k0 = next_k0;
     width = next_width;
   }
+  if (rest_deferred && (rc = run_deferred(&rest_deferred)) != 0) return finish(rc);   // not reached: a panel with rows below has a successor
   if (rest_pending) {
     hipStreamWaitEvent(stream, ev_rest, 0);
     rest_pending = false;

@@ -13,7 +13,8 @@
 // IN:  int32 n, p, method, flags; float64 u, small; the n x p panel,
 //      column-major (lda = n).
 // OUT: the panel after the factorization, then int32 perm[p], piv[p],
-//      float64 d[2p], int32 nelim, status.
+//      float64 d[2p], int32 nelim, status, crow[p] (relaxed: the A21 row
+//      behind each row of C, -1 for none; other rules: -2).
 // The workspace is filled with 0xff bytes (NaN doubles) first, as memory the
 // kernels must write before they read.
 
@@ -99,6 +100,8 @@ int main(int argc, char** argv) {
                                reinterpret_cast<double*>(base + ws.wb_off), nullptr);
   }
   must(rc == 0, "a launcher returned an error");
+  std::vector<int> crow(p, -2);   // relaxed: the A21 row behind each row of C
+  if (method == CTP_RELAXED) memcpy(crow.data(), base + ws.crow_off, sizeof(int) * (size_t)p);
   free(base);
 
   FILE* o = fopen(argv[2], "wb");
@@ -109,6 +112,7 @@ int main(int argc, char** argv) {
   fwrite(d.data(), sizeof(double), 2 * (size_t)p, o);
   fwrite(&nelim, sizeof(int), 1, o);
   fwrite(&status, sizeof(int), 1, o);
+  fwrite(crow.data(), sizeof(int), p, o);
   fclose(o);
   return 0;
 }

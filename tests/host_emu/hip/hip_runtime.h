@@ -66,6 +66,10 @@ typedef enum hipMemcpyKind {
 } hipMemcpyKind;
 typedef enum hipFuncAttribute { hipFuncAttributeMaxDynamicSharedMemorySize = 8 } hipFuncAttribute;
 
+struct alignas(16) uint4 {
+  unsigned x, y, z, w;
+};
+
 struct dim3 {
   unsigned x, y, z;
   constexpr dim3(unsigned x_ = 1, unsigned y_ = 1, unsigned z_ = 1) : x(x_), y(y_), z(z_) {}
@@ -401,6 +405,8 @@ inline void emu_wave_barrier() {
 
 inline int emu_readfirstlane(int v) { return ::emu::shuffle(v, 0); }
 #define __builtin_amdgcn_readfirstlane emu_readfirstlane
+inline int emu_readlane(int v, int src) { return ::emu::shuffle(v, src); }
+#define __builtin_amdgcn_readlane emu_readlane
 
 inline int emu_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
   if (row_mask != 0xf || bank_mask != 0xf) ::emu::fail("DPP row/bank masks not emulated");

@@ -91,7 +91,12 @@ def test_batched_dense_matches_oracle_and_single_driver(method, S, N, pw, n_smal
         assert torch.equal(f1["piv"], f["piv"][s]), s
         assert torch.equal(f1["d"], f["d"][s]), s
         assert torch.equal(a1, a[s]), s
-        assert int(f1["status"].item()) == int(f["status"][s].item()), s
+        # the status words agree except for the rescan bit: it reports how
+        # the relaxed compression found C (the batched one walks top-8 lists
+        # and rescans; the single driver's panels of at most 16384 rows walk
+        # exact lists and never do), not a property of the result
+        keep = ~ctp.CTP_STATUS_RELAXED_RESCAN
+        assert int(f1["status"].item()) & keep == int(f["status"][s].item()) & keep, s
         # the oracle: decisions exactly, values to the bound of this draw
         assert (f["perm"][s].cpu().numpy() == ref.perm).all(), s
         assert (f["piv"][s].cpu().numpy() == ref.piv).all(), s
