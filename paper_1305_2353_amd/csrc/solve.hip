@@ -77,8 +77,9 @@ int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const 
 // so that the rows of the result are [ W_E , X_d - W_E L_dE^T ]: W of the
 // eliminated columns and the updated delayed columns at once.  The columns
 // go in panels of up to 256:
-//   gather   X into the workspace, L' (masked as above) into a compact
-//            p x p copy lc;
+//   gather   L' (masked as above) into a compact p x p copy lc (the
+//            batched Solve also copies X into the workspace; the single
+//            one reads X from A21 through perm in the diagonal kernels);
 //   diag     per panel: a workgroup of four waves takes 64 rows (16 per
 //            wave) and solves them against the panel's diagonal block of
 //            L', right-looking in 16-column blocks held as FP64
@@ -99,6 +100,18 @@ int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const 
 constexpr int SV_PANEL = 256;             // columns per panel
 constexpr int SV_LDW = 17;                // LDS stride of a 16-entry column (padded)
 
+// Column j of L' (rows 0..p-1) into lc.
+CTP_DEV void solve_lc_body(int p, const double* __restrict__ a, int lda, const int* __restrict__ piv,
+                           const int* __restrict__ nelim_p, double* __restrict__ lc, int j) {
+  const int nelim = min(max(*nelim_p, 0), p);
+  const int pj = piv[j];
+  const bool col = j < nelim && pj != PIV_ZERO;
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    const bool keep = col && i > j && !(i == j + 1 && pj == PIV_2X2_FIRST);
+    lc[(size_t)j * p + i] = keep ? a[(size_t)j * lda + i] : (i == j ? 1.0 : 0.0);
+  }
+}
+
 // X column j (rows chunk*4096..) = A21 column perm[j]; with the first chunk,
 // column j of L' (rows 0..p-1) into lc.
 CTP_DEV void solve_gather_body(int r, int p, const double* __restrict__ a, int lda, const int* __restrict__ perm,
@@ -109,15 +122,15 @@ CTP_DEV void solve_gather_body(int r, int p, const double* __restrict__ a, int l
   const int i0 = chunk * 4096;
   const int i1 = min(r, i0 + 4096);
   for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
-  if (chunk == 0) {
-    const int nelim = min(max(*nelim_p, 0), p);
-    const int pj = piv[j];
-    const bool col = j < nelim && pj != PIV_ZERO;
-    for (int i = threadIdx.x; i < p; i += blockDim.x) {
-      const bool keep = col && i > j && !(i == j + 1 && pj == PIV_2X2_FIRST);
-      lc[(size_t)j * p + i] = keep ? a[(size_t)j * lda + i] : (i == j ? 1.0 : 0.0);
-    }
-  }
+  if (chunk == 0) solve_lc_body(p, a, lda, piv, nelim_p, lc, j);
+}
+
+// Column j of L' alone (the single-panel Solve, whose diagonal kernels read
+// X straight from A21 through perm).
+__global__ __launch_bounds__(256) void solve_lc_kernel(int p, const double* __restrict__ a, int lda,
+                                                     const int* __restrict__ piv, const int* __restrict__ nelim_p,
+                                                     double* __restrict__ lc) {
+  solve_lc_body(p, a, lda, piv, nelim_p, lc, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a, int lda,
@@ -208,10 +221,15 @@ CTP_DEV void sv_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier"
 // through registers (fetched at the start of an iteration, written to LDS
 // at its end): the memory traffic is spread over the whole loop and hidden
 // behind the arithmetic of the current block.
+//
+// xsrc (optional): the panel's own X columns are read from A21 (xsrc, leading
+// dimension ldsrc) through perm instead of from x, so that no gather pass
+// copies them into the workspace first; the results go to x as before.
 template <int PREC, int NBP>
 CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, int nelim, double* __restrict__ x,
                            int ldx, const double* __restrict__ lc, typename SvArith<PREC>::T* lsh,
-                           typename SvArith<PREC>::T* stage, int r0) {
+                           typename SvArith<PREC>::T* stage, int r0, const double* __restrict__ xsrc = nullptr,
+                           int ldsrc = 0, const int* __restrict__ perm = nullptr) {
   using A = SvArith<PREC>;
   using T = typename A::T;
   using acc_t = typename A::acc_t;
@@ -219,7 +237,7 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
   const int ga = lane >> 4, c = lane & 15;
   const int nbe = min(NBP, (nelim - c0 + 15) / 16);   // blocks of the panel with eliminated columns
   const int nkc = (min(c0, nelim) + 7) / 8;            // 8-column chunks of earlier eliminated columns
-  if (nbe <= 0 && nkc == 0) return;                    // nothing updates this panel: X is final
+  if (nbe <= 0 && nkc == 0 && !xsrc) return;           // nothing updates this panel: X is final
   const int nb = min(NBP, (p - c0 + 15) / 16);         // blocks with columns below p
   int rows[4];
 #pragma unroll
@@ -257,10 +275,18 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
       if (m < NBP - b) buf[16 * m] = lreg[h];
     }
   };
+  // (direct reads: the A21 column behind position j is perm[j]; load_x is
+  // issued an iteration ahead of its use, which covers the extra load)
   auto load_x = [&](int b, T* v) __attribute__((always_inline)) {
     const int j = min(c0 + 16 * b + c, p - 1);
+    if (xsrc) {
+      const double* col = xsrc + (size_t)perm[j] * ldsrc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (T)x[(size_t)j * ldx + rows[q]];
+      for (int q = 0; q < 4; ++q) v[q] = (T)col[rows[q]];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = (T)x[(size_t)j * ldx + rows[q]];
+    }
   };
   // a wave with rows below r stores all 16 of its rows: the rows past r
   // (up to the next multiple of 16) are padding of x, whose leading
@@ -273,6 +299,15 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
       for (int q = 0; q < 4; ++q) x[(size_t)j * ldx + r0 + A::row(ga, q)] = (double)v[q];
     }
   };
+  if (nbe <= 0 && nkc == 0) {
+    // nothing updates this panel: its X, read from A21, is final
+    for (int b = 0; b < nb; ++b) {
+      T v[4];
+      load_x(b, v);
+      store_x(b, v);
+    }
+    return;
+  }
   acc_t acc[NBP];
 #pragma unroll
   for (int k = 0; k < NBP; ++k) acc[k] = acc_t{0, 0, 0, 0};
@@ -444,7 +479,9 @@ CTP_DEV void solve_diag_wg(int r, int p, int c0, const int* __restrict__ piv, in
 template <int PREC, int NBP>
 __global__ __launch_bounds__(256, 2) void solve_diag_kernel(int r, int p, int c0, const int* __restrict__ piv,
                                                           const int* __restrict__ nelim_p, double* __restrict__ x,
-                                                          int ldx, const double* __restrict__ lc) {
+                                                          int ldx, const double* __restrict__ lc,
+                                                          const double* __restrict__ a21, int lda,
+                                                          const int* __restrict__ perm) {
   using T = typename SvArith<PREC>::T;
   __shared__ T lsh[2 * SV_LBUF];
   __shared__ T stage[4][16 * SV_LDW];
@@ -452,7 +489,8 @@ __global__ __launch_bounds__(256, 2) void solve_diag_kernel(int r, int p, int c0
   if ((int)blockIdx.x * 64 >= r) return;
   // waves past the last row still take part in the staging and barriers
   const int r0 = (blockIdx.x * 4 + wave) * 16;
-  solve_diag_wg<PREC, NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, lsh, stage[wave], r0);
+  solve_diag_wg<PREC, NBP>(r, p, c0, piv, min(max(*nelim_p, 0), p), x, ldx, lc, lsh, stage[wave], r0, a21, lda,
+                           perm);
 }
 
 // Rows chunk*4096.. of column k: the workspace holds W (eliminated) or the
@@ -548,15 +586,20 @@ int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* p
   const int r = n - p;
   if (r <= 0 || p <= 0) return 0;
   const dim3 cols((r + 4095) / 4096, p);
-  solve_gather_kernel<<<cols, 256, 0, stream>>>(r, p, a, lda, perm, piv, nelim, w, ldw, lc);
+  // L' only: the diagonal kernels read X from A21 through perm themselves
+  solve_lc_kernel<<<p, 256, 0, stream>>>(p, a, lda, piv, nelim, lc);
   const unsigned grid = (unsigned)((r + 63) / 64);
+  const double* a21 = a + p;
   for (int c0 = 0; c0 < p; c0 += SV_PANEL) {
     const int nbp = (min(SV_PANEL, p - c0) + 15) / 16;
     solve_diag_dispatch(nbp, [&](auto k) {
       constexpr int NBP = decltype(k)::value;
-      if (prec == 1) solve_diag_kernel<1, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
-      else if (prec == 2) solve_diag_kernel<2, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
-      else solve_diag_kernel<0, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc);
+      if (prec == 1)
+        solve_diag_kernel<1, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc, a21, lda, perm);
+      else if (prec == 2)
+        solve_diag_kernel<2, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc, a21, lda, perm);
+      else
+        solve_diag_kernel<0, NBP><<<grid, 256, 0, stream>>>(r, p, c0, piv, nelim, w, ldw, lc, a21, lda, perm);
     });
   }
   solve_scale_kernel<<<cols, 256, 0, stream>>>(r, p, a, lda, piv, d, nelim, w, ldw);
