@@ -77,9 +77,8 @@ int launch_form_w(int n, int p, const double* a, int lda, const int* piv, const 
 // so that the rows of the result are [ W_E , X_d - W_E L_dE^T ]: W of the
 // eliminated columns and the updated delayed columns at once.  The columns
 // go in panels of up to 256:
-//   gather   L' (masked as above) into a compact p x p copy lc (the
-//            batched Solve also copies X into the workspace; the single
-//            one reads X from A21 through perm in the diagonal kernels);
+//   lc       L' (masked as above) into a compact p x p copy (X is not
+//            copied: the diagonal kernels read it from A21 through perm);
 //   diag     per panel: a workgroup of four waves takes 64 rows (16 per
 //            wave) and solves them against the panel's diagonal block of
 //            L', right-looking in 16-column blocks held as FP64
@@ -112,32 +111,12 @@ CTP_DEV void solve_lc_body(int p, const double* __restrict__ a, int lda, const i
   }
 }
 
-// X column j (rows chunk*4096..) = A21 column perm[j]; with the first chunk,
-// column j of L' (rows 0..p-1) into lc.
-CTP_DEV void solve_gather_body(int r, int p, const double* __restrict__ a, int lda, const int* __restrict__ perm,
-                               const int* __restrict__ piv, const int* __restrict__ nelim_p, double* __restrict__ x,
-                               int ldx, double* __restrict__ lc, int j, int chunk) {
-  const double* src = a + p + (size_t)perm[j] * lda;
-  double* dst = x + (size_t)j * ldx;
-  const int i0 = chunk * 4096;
-  const int i1 = min(r, i0 + 4096);
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) dst[i] = src[i];
-  if (chunk == 0) solve_lc_body(p, a, lda, piv, nelim_p, lc, j);
-}
-
-// Column j of L' alone (the single-panel Solve, whose diagonal kernels read
-// X straight from A21 through perm).
+// Column j of L' (the diagonal kernels read X straight from A21 through
+// perm, so nothing else is gathered).
 __global__ __launch_bounds__(256) void solve_lc_kernel(int p, const double* __restrict__ a, int lda,
                                                      const int* __restrict__ piv, const int* __restrict__ nelim_p,
                                                      double* __restrict__ lc) {
   solve_lc_body(p, a, lda, piv, nelim_p, lc, blockIdx.x);
-}
-
-__global__ __launch_bounds__(256) void solve_gather_kernel(int r, int p, const double* __restrict__ a, int lda,
-                                                         const int* __restrict__ perm, const int* __restrict__ piv,
-                                                         const int* __restrict__ nelim_p, double* __restrict__ x,
-                                                         int ldx, double* __restrict__ lc) {
-  solve_gather_body(r, p, a, lda, perm, piv, nelim_p, x, ldx, lc, blockIdx.y, blockIdx.x);
 }
 
 // DPP move of a double: every lane <- lane k of its row of 16.
@@ -534,14 +513,12 @@ __global__ __launch_bounds__(256) void solve_scale_kernel(int r, int p, double* 
   solve_scale_body(r, p, a, lda, piv, d, nelim_p, w, ldw, blockIdx.y, blockIdx.x);
 }
 
-// Batched: the node is blockIdx.z (gather, scale) or blockIdx.y (diag).
-__global__ __launch_bounds__(256) void solve_gather_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
+// Batched: the node is blockIdx.z (L', scale) or blockIdx.y (diag).
+__global__ __launch_bounds__(256) void solve_lc_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
   const BatchNode& nd = nodes[blockIdx.z];
-  const int r = nd.n - nd.p;
-  if ((int)blockIdx.y >= nd.p || (int)blockIdx.x * 4096 >= r) return;
+  if ((int)blockIdx.y >= nd.p || nd.n - nd.p <= 0) return;
   const Workspace ws = workspace_layout(nd.n, nd.p, method);
-  solve_gather_body(r, nd.p, nd.a, nd.lda, nd.perm, nd.piv, nd.nelim, reinterpret_cast<double*>(nd.work + ws.w_off),
-                    ws.ldw, reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y, blockIdx.x);
+  solve_lc_body(nd.p, nd.a, nd.lda, nd.piv, nd.nelim, reinterpret_cast<double*>(nd.work + ws.lc_off), blockIdx.y);
 }
 
 template <int PREC, int NBP>
@@ -558,7 +535,8 @@ __global__ __launch_bounds__(256, 2) void solve_diag_batch_kernel(const BatchNod
   // the node's panel may be narrower than NBP blocks: the extra blocks are
   // past p (their columns are neither read nor written)
   solve_diag_wg<PREC, NBP>(r, nd.p, c0, nd.piv, min(max(*nd.nelim, 0), nd.p), reinterpret_cast<double*>(nd.work + ws.w_off),
-                     ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), lsh, stage[wave], r0);
+                     ws.ldw, reinterpret_cast<const double*>(nd.work + ws.lc_off), lsh, stage[wave], r0, nd.a + nd.p,
+                     nd.lda, nd.perm);
 }
 
 __global__ __launch_bounds__(256) void solve_scale_batch_kernel(const BatchNode* __restrict__ nodes, int method) {
@@ -579,7 +557,7 @@ static void solve_diag_dispatch(int nbp, F&& f) {
 }
 
 // prec 0: FP64 throughout; 1 / 2: the triangular solve in FP32 on the FP32 /
-// BF16 matrix cores (FP32 accumulation); the gather, the 2x2 inverses and
+// BF16 matrix cores (FP32 accumulation); the copy of L', the 2x2 inverses and
 // D^-1 stay FP64.
 int launch_solve(int n, int p, double* a, int lda, const int* perm, const int* piv, const double* d,
                  const int* nelim, double* w, int ldw, double* lc, int prec, hipStream_t stream) {
@@ -611,7 +589,7 @@ int launch_solve_batch(int count, const BatchNode* nodes, int method, int max_p,
                        hipStream_t stream) {
   if (count <= 0 || max_r <= 0 || max_p <= 0) return 0;
   const dim3 cols((max_r + 4095) / 4096, max_p, count);
-  solve_gather_batch_kernel<<<cols, 256, 0, stream>>>(nodes, method);
+  solve_lc_batch_kernel<<<dim3(1, max_p, count), 256, 0, stream>>>(nodes, method);
   const dim3 grid((max_r + 63) / 64, count);
   for (int c0 = 0; c0 < max_p; c0 += SV_PANEL) {
     const int nbp = (min(SV_PANEL, max_p - c0) + 15) / 16;
