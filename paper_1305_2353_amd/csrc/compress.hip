@@ -233,12 +233,27 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
     int ti[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) { tv[q] = -1.0; ti[q] = 0x7fffffff; }
+    // a chunk's K candidates are requested together, and the next chunk's
+    // while this one is merged (the loads do not wait for the comparisons)
+    const Cand* src = cand + (size_t)col * nchunks * K;
+    Cand nxt[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) nxt[q] = src[q];
     for (int ch = 0; ch < nchunks; ++ch) {
-      const Cand* src = cand + ((size_t)col * nchunks + ch) * K;
+      Cand cur[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) cur[q] = nxt[q];
+      if (ch + 1 < nchunks) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) nxt[q] = src[(size_t)(ch + 1) * K + q];
+      }
+      bool live = true;
+#pragma unroll
       for (int q = 0; q < K; ++q) {
-        Cand e = src[q];
-        if (e.v < 0.0) break;
-        if (!better(e.v, e.i, tv[K - 1], ti[K - 1])) break;   // lists are sorted
+        const Cand e = cur[q];
+        // lists are sorted: the first missing or losing entry ends the chunk
+        live = live && e.v >= 0.0 && better(e.v, e.i, tv[K - 1], ti[K - 1]);
+        if (!live) continue;
         double cv = e.v;
         int ci = e.i;
 #pragma unroll
@@ -276,23 +291,27 @@ CTP_DEV void relaxed_select_body(int r, int p, const double* __restrict__ a21, i
       int taken = s_taken;
       int jj = j;
       int need = 0;
+      // the next column's candidates are read while this one's flags are
+      // tested (they do not depend on the flags)
+      int ahead = lane < K && jj < p ? lists[(size_t)jj * K + lane].i : -1;
       for (; jj < p; ++jj) {
+        const int row = ahead;
+        ahead = lane < K && jj + 1 < p ? lists[(size_t)(jj + 1) * K + lane].i : -1;
         if (taken >= r) {
           if (lane == 0) chosen[jj] = -1;
           continue;
         }
-        const int row = lane < K ? lists[(size_t)jj * K + lane].i : -1;
-        const bool free_row = row >= 0 && !((flags[row >> 5] >> (row & 31)) & 1u);
-        const unsigned long long m = __ballot(free_row);
+        const bool ok = (unsigned)row < (unsigned)r;   // not a missing candidate
+        const unsigned fw = flags[ok ? row >> 5 : 0];
+        const unsigned long long m = __ballot((int)((unsigned)ok & ~(fw >> (row & 31)) & 1u));
         if (m == 0ull) {
           need = 1;
           break;
         }
-        const int q = __ffsll((long long)m) - 1;
-        const int pick = __shfl(row, q, 64);
+        const int pick = __builtin_amdgcn_readlane(row, __ffsll((long long)m) - 1);
         if (lane == 0) {
           chosen[jj] = pick;
-          flags[pick >> 5] |= 1u << (pick & 31);
+          atomicOr(&flags[pick >> 5], 1u << (pick & 31));
         }
         wave_sync();   // the flag is set before any lane tests the next column
         ++taken;
