@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import assert_parity, rel_err, require_gpu, schur_factors, schur_tol
+from gpu_helpers import FP64_TOL, assert_parity, rel_err, require_gpu, schur_factors, schur_tol
 from oracle.supernode import factor_supernode, schur_rows
 from workloads import batch_panel, supernode
 
@@ -74,7 +74,7 @@ def test_fused_supernode_matches_steps_and_oracle(method, shape):
     assert (np.tril(S) == np.tril(s2.cpu().numpy())).all()
     # and the oracle
     S_ref = schur_rows(ref, np.arange(r))
-    assert rel_err(np.tril(S), np.tril(S_ref)) <= schur_tol(*schur_factors(ref, p), S_ref)
+    assert rel_err(np.tril(S), np.tril(S_ref)) <= FP64_TOL, schur_tol(*schur_factors(ref, p), S_ref)
     # packed tiles: the same values
     opts_t = ctp.ctp_default_opts(method, flags=ctp.CTP_FLAG_S_TILED)
     a2 = ctp.device_panel(A)
@@ -126,4 +126,4 @@ def test_batched_tasks_one_at_a_time(method, tiled):
         if form[i] and n > p:
             S = parts.s_view(i).cpu().numpy()
             S_ref = schur_rows(ref, np.arange(n - p))
-            assert rel_err(np.tril(S), np.tril(S_ref)) <= schur_tol(*schur_factors(ref, p), S_ref), i
+            assert rel_err(np.tril(S), np.tril(S_ref)) <= FP64_TOL, (i, schur_tol(*schur_factors(ref, p), S_ref))
