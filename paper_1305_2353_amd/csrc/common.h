@@ -50,7 +50,7 @@ CTP_DEV void wave_sync() {
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-constexpr int RELAXED_CHUNK = 8192;   // rows per (column, chunk) block of the relaxed compression
+constexpr int RELAXED_CHUNK = 16384;  // rows per (column, chunk) block of the relaxed compression
 constexpr int PIV_NSLOT = 8;          // pending eliminated columns per batch of the pivot search
 constexpr int PIV_STATE_BYTES = 256;  // pivot-search state carried between launches
 constexpr int TPP_MAX_GROUPS_WS = 4096; // grid-wide TPP: workgroups of a step (64 rows each)

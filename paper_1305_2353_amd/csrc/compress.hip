@@ -146,20 +146,31 @@ CTP_DEV void relaxed_topk_body(int r, int p, const double* __restrict__ a21, int
 #pragma unroll
   for (int q = 0; q < K; ++q) { tv[q] = -1.0; ti[q] = 0x7fffffff; }
   bool finite = true;
-  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    double v = fabs(colp[i]);
-    finite = finite && isfinite(v);
-    if (better(v, i, tv[K - 1], ti[K - 1])) {
-      // insertion into the sorted list (static indices only)
-      double cv = v;
-      int ci = i;
+  // eight loads in flight per thread (unconditional: rows past the chunk
+  // read its last row and are skipped), then the insertions in row order
+  constexpr int RU = 8;
+  const int nt = blockDim.x;
+  for (int ib = i0 + threadIdx.x; ib < i1; ib += RU * nt) {
+    double vb[RU];
 #pragma unroll
-      for (int q = 0; q < K; ++q) {
-        if (better(cv, ci, tv[q], ti[q])) {
-          double sv = tv[q];
-          int si = ti[q];
-          tv[q] = cv; ti[q] = ci;
-          cv = sv; ci = si;
+    for (int u = 0; u < RU; ++u) vb[u] = colp[min(ib + u * nt, i1 - 1)];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int i = ib + u * nt;
+      const double v = fabs(vb[u]);
+      if (i < i1) finite = finite && isfinite(v);
+      if (i < i1 && better(v, i, tv[K - 1], ti[K - 1])) {
+        // insertion into the sorted list (static indices only)
+        double cv = v;
+        int ci = i;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+          if (better(cv, ci, tv[q], ti[q])) {
+            double sv = tv[q];
+            int si = ti[q];
+            tv[q] = cv; ti[q] = ci;
+            cv = sv; ci = si;
+          }
         }
       }
     }

@@ -93,7 +93,7 @@ def test_nonfinite_status(method, case):
 
 def _rescan_panel(n=20000, p=16, seed=3):
     # Nine rows of A21 larger than every other entry in every column, spread
-    # over three 8192-row chunks: each column's eight best rows are among
+    # over the row chunks of the top-8 lists: each column's eight best rows are among
     # them, so once nine columns have taken them the later columns find all
     # eight candidates taken and rescan the column.
     rng = np.random.default_rng(seed)
