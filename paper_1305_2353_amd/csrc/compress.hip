@@ -690,6 +690,7 @@ int launch_compress(int n, int p, const double* a, int lda, int method, double* 
                     int* crow, int* status, void* work, hipStream_t stream) {
   const int r = n - p;
   const double* a21 = a + p;
+  if (p <= 0) return method == CTP_STRICT || method == CTP_RELAXED ? 0 : -5;   // C is empty
   Workspace ws = workspace_layout(n, p, method);
   unsigned char* base = static_cast<unsigned char*>(work);
   if (method == CTP_STRICT) {
