@@ -142,6 +142,16 @@ __global__ __launch_bounds__(512) void dense_bookkeep_batch_kernel(int N, const 
 }
 
 // gperm[i] = i mod N over count systems of order N
+// nelim and status of the panel just factorized, into pinned host memory
+// (the host reads them after the stream synchronizes): one tiny kernel
+// instead of two device-to-host copies.
+__global__ void dense_publish_kernel(const int* __restrict__ nelim, const int* __restrict__ status,
+                                     volatile int* out) {
+  out[0] = *nelim;
+  out[1] = *status;
+  __threadfence_system();
+}
+
 __global__ void dense_iota_kernel(int* gperm, int N, long long total) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < total) gperm[i] = (int)(i % N);
@@ -666,6 +676,17 @@ static int run_deferred(void* f) {
   return step ? step() : 0;
 }
 
+// Pinned, device-visible (nelim, status) pair per host thread and device;
+// allocated on first use and kept (a few bytes) for the thread's lifetime.
+static volatile int* dense_readback() {
+  static thread_local int* buf[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!buf[dev] && hipHostMalloc(reinterpret_cast<void**>(&buf[dev]), 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    buf[dev] = nullptr;
+  return buf[dev];
+}
+
 static hipStream_t dense_stream(int which) {
   static hipStream_t st[64][2] = {};
   static std::mutex m;
@@ -718,6 +739,7 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
     return CTP_ERR_HIP_BASE - (int)hipGetLastError();
   }
   bool rest_pending = false;
+  volatile int* readback = dense_readback();   // null: read back with copies instead
   std::function<int()> rest_deferred;   // part 1 of the last panel's trailing update, not yet enqueued
   // every exit: the chain takes over the side stream's last work, the
   // caller's stream takes over the chain
@@ -760,10 +782,16 @@ int ctp_ldlt_dense(int N, int pw, double* a, int lda, const ctp_opts* opts, int*
                              rest_deferred ? run_deferred : nullptr, &rest_deferred);
     if (rc) return finish(rc);
     int ne = 0, st = 0;
-    if (hipMemcpyAsync(&ne, pnelim, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipMemcpyAsync(&st, pstatus, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
+    if (readback) {
+      dense_publish_kernel<<<1, 1, 0, stream>>>(pnelim, pstatus, readback);
+      if (hipStreamSynchronize(stream) != hipSuccess) return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+      ne = readback[0];
+      st = readback[1];
+    } else if (hipMemcpyAsync(&ne, pnelim, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+               hipMemcpyAsync(&st, pstatus, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+               hipStreamSynchronize(stream) != hipSuccess) {
       return finish(CTP_ERR_HIP_BASE - (int)hipGetLastError());
+    }
     acc_status |= st;
     ++panels;
     // the previous panel's remaining update is done before this panel's
