@@ -178,6 +178,7 @@ TSAN_CASES = [
 LARGE_CASES = [
     (300, 130, "relaxed", 0, 7, ()),                # decide/apply, 512 threads
     (300, 130, "strict", 0, 8, ()),
+    (900, 400, "relaxed", 0, 11, ()),               # exact lists too large for LDS: the walk reads them in place
 ]
 
 
