@@ -611,8 +611,8 @@ __global__ __launch_bounds__(EXACT_THREADS) void relaxed_exact_kernel(int r, int
 // One workgroup; wave 0 walks the columns in order and takes the first row
 // of column j's list not taken yet (there is one: the list holds j+1
 // distinct rows and j rows are taken); lanes test 4 x 64 list entries per
-// step, and the next column's first entries are read while the flags of
-// this one are tested.  The choices stay in LDS until the walk ends.  Dynamic LDS: a bitmap
+// step, four columns at a time.  The choices stay in LDS until the walk
+// ends.  Dynamic LDS: a bitmap
 // of the rows taken, the chosen rows (p ints), then (LDS_LISTS) the lists,
 // 16-byte aligned.
 template <bool LDS_LISTS>
@@ -642,40 +642,83 @@ __global__ __launch_bounds__(1024) void relaxed_walk_kernel(int r, int p, const 
 #pragma unroll
       for (int t = 0; t < 4; ++t) row[t] = (int)L[min(c0 + 64 * t + lane, j)];
     };
-    int ahead[4] = {0, 0, 0, 0};
-    if (m > 0) load4(0, 0, ahead);
-    for (int j = 0; j < p; ++j) {
-      int pick = -1;
-      if (j < m) {                           // else every row is taken
-        int row[4] = {ahead[0], ahead[1], ahead[2], ahead[3]};
-        if (j + 1 < m) load4(j + 1, 0, ahead);   // the next list does not depend on the flags
-        for (int c0 = 0;;) {
-          unsigned fw[4];
+    // Columns go in groups of four: the first 256 entries of the four lists
+    // and their flag words are read together, then the picks are taken in
+    // column order in registers, each excluding the rows picked before it
+    // in the group (so the flags seen by column j + t are those before the
+    // group plus the group's earlier picks, as in the sequential walk).  A
+    // column with no free row among its first 256 entries ends the group and
+    // continues through the rest of its list once the group's picks are set.
+    for (int j0 = m + lane; j0 < p; j0 += 64) chosen[j0] = -1;   // every row is taken
+    int j = 0;
+    while (j < m) {
+      const int g = min(4, m - j);
+      int rows[4][4];
+      unsigned fw[4][4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) fw[t] = flags[(unsigned)row[t] < (unsigned)r ? row[t] >> 5 : 0];   // all four in flight
+      for (int t = 0; t < 4; ++t) load4(min(j + t, m - 1), 0, rows[t]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) fw[t][u] = flags[(unsigned)rows[t][u] < (unsigned)r ? rows[t][u] >> 5 : 0];
+      int picks[4] = {-1, -1, -1, -1};
+      int done = 0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= g || done < t) break;       // uniform: the previous column was resolved here
+        unsigned long long bal[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int rw = rows[t][u];
+          unsigned ok = (unsigned)(64 * u + lane <= j + t) & (unsigned)((unsigned)rw < (unsigned)r);
+          ok &= ~(fw[t][u] >> (rw & 31)) & 1u;
+          ok &= (unsigned)(rw != picks[0]) & (unsigned)(rw != picks[1]) & (unsigned)(rw != picks[2]);
+          bal[u] = __ballot((int)ok);
+        }
+        const int u = bal[0] ? 0 : bal[1] ? 1 : bal[2] ? 2 : bal[3] ? 3 : -1;   // uniform
+        if (u >= 0) {
+          const unsigned long long b = u == 0 ? bal[0] : u == 1 ? bal[1] : u == 2 ? bal[2] : bal[3];
+          const int rsel = u == 0 ? rows[t][0] : u == 1 ? rows[t][1] : u == 2 ? rows[t][2] : rows[t][3];
+          picks[t] = __builtin_amdgcn_readlane(rsel, __ffsll((long long)b) - 1);
+          done = t + 1;
+        }
+      }
+      if (lane < done) {
+        const int pk = lane == 0 ? picks[0] : lane == 1 ? picks[1] : lane == 2 ? picks[2] : picks[3];
+        chosen[j + lane] = pk;
+        atomicOr(&flags[pk >> 5], 1u << (pk & 31));
+      }
+      wave_sync();   // the group's flags are set before any lane tests a later column
+      j += done;
+      if (done < g) {
+        // column j: its first 256 entries are taken; the rest of its list
+        int pick = -1;
+        int row[4];
+        for (int c0 = 256; c0 <= j && pick < 0; c0 += 256) {
+          load4(j, c0, row);
+          unsigned f1[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) f1[t] = flags[(unsigned)row[t] < (unsigned)r ? row[t] >> 5 : 0];
           unsigned long long bal[4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {   // bitwise, not short-circuit: no branches
+          for (int t = 0; t < 4; ++t) {
             const unsigned ok = (unsigned)(c0 + 64 * t + lane <= j) & (unsigned)((unsigned)row[t] < (unsigned)r);
-            bal[t] = __ballot((int)(ok & ~(fw[t] >> (row[t] & 31)) & 1u));
+            bal[t] = __ballot((int)(ok & ~(f1[t] >> (row[t] & 31)) & 1u));
           }
           const int t = bal[0] ? 0 : bal[1] ? 1 : bal[2] ? 2 : bal[3] ? 3 : -1;   // uniform
           if (t >= 0) {
             const unsigned long long b = t == 0 ? bal[0] : t == 1 ? bal[1] : t == 2 ? bal[2] : bal[3];
             const int rsel = t == 0 ? row[0] : t == 1 ? row[1] : t == 2 ? row[2] : row[3];
             pick = __builtin_amdgcn_readlane(rsel, __ffsll((long long)b) - 1);
-            break;
           }
-          c0 += 256;
-          if (c0 > j) break;                 // not reached: the list holds a free row
-          load4(j, c0, row);
         }
+        if (lane == 0) {
+          chosen[j] = pick;                  // -1 is not reached: the list holds a free row
+          if (pick >= 0) atomicOr(&flags[pick >> 5], 1u << (pick & 31));
+        }
+        wave_sync();
+        ++j;
       }
-      if (lane == 0) {
-        chosen[j] = pick;
-        if (pick >= 0) atomicOr(&flags[pick >> 5], 1u << (pick & 31));   // no read round trip
-      }
-      wave_sync();   // the flag is set before any lane tests the next column
     }
   }
   __syncthreads();
